@@ -1,0 +1,120 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case swaps one oracle function for a plausible wrong variant (a dropped
+factor, a transposed operand, a wrong sign or index) on the CPU and checks
+that at least one pin test then fails.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import test_oracle_pins as pins
+from oracle import exactsim as ox
+from oracle import simrank as sr
+
+
+def _power_method_transposed(g, c, iters=60):
+    n = g.n
+    S = np.eye(n)
+    for _ in range(iters):
+        S = c * (g.P @ (g.P @ S).T).T  # P S P^T instead of P^T S P
+        np.fill_diagonal(S, 1.0)
+    return S
+
+
+def _power_method_no_diag_reset(g, c, iters=60):
+    S = np.eye(g.n)
+    for _ in range(iters):
+        S = c * (g.PT @ (g.PT @ S).T).T
+    return S
+
+
+def _forward_without_restart_factor(g, u, c, L):
+    levels, pi = _orig_forward(g, u, c, L)
+    sc = math.sqrt(c)
+    return levels / (1 - sc), pi / (1 - sc)
+
+
+def _forward_sqrt_dropped(g, u, c, L):
+    # uses c instead of sqrt(c) per hop
+    n = g.n
+    levels = np.zeros((L + 1, n))
+    levels[0, u] = 1 - math.sqrt(c)
+    for l in range(1, L + 1):
+        levels[l] = c * (g.P @ levels[l - 1])
+    return levels, levels.sum(0)
+
+
+def _back_with_P(g, levels, D, c):
+    sc = math.sqrt(c)
+    a = 1.0 / (1.0 - sc)
+    L = levels.shape[0] - 1
+    s = a * (D * levels[L])
+    for l in range(1, L + 1):
+        s = sc * (g.P @ s) + a * (D * levels[L - l])  # P instead of P^T
+    return s
+
+
+def _back_wrong_level(g, levels, D, c):
+    sc = math.sqrt(c)
+    a = 1.0 / (1.0 - sc)
+    L = levels.shape[0] - 1
+    s = a * (D * levels[0])
+    for l in range(1, L + 1):
+        s = sc * (g.inv_din * (g.AT @ s)) + a * (D * levels[l])  # levels in the wrong order
+    return s
+
+
+def _diag_flipped(Rk, M, din, c, exact_small_din=True):
+    D = _orig_diag(Rk, M, din, c, exact_small_din)
+    has = Rk > 0
+    D[has] = M[has].astype(np.float64) / Rk[has].astype(np.float64)  # meeting fraction
+    return D
+
+
+def _exact_diag_no_c(g, S, c):
+    return _orig_exact_diag(g, S, 1.0)
+
+
+def _levels_off_by_one(c, eps):
+    return _orig_levels(c, eps) - 1
+
+
+_orig_forward = ox.forward_levels
+_orig_diag = ox.diag_estimate
+_orig_exact_diag = sr.exact_diagonal
+_orig_levels = ox.num_levels
+
+MUTANTS = [
+    ("power_method_transposed", sr, "power_method", _power_method_transposed,
+     [lambda: pins.test_power_method_matches_direct_solve(0), lambda: pins.test_power_method_matches_direct_solve(1)]),
+    ("power_method_no_diag_reset", sr, "power_method", _power_method_no_diag_reset,
+     [lambda: pins.test_power_method_complete_graph(3)]),
+    ("forward_no_restart_factor", ox, "forward_levels", _forward_without_restart_factor,
+     [pins.test_forward_cycle_closed_form]),
+    ("forward_c_not_sqrt_c", ox, "forward_levels", _forward_sqrt_dropped,
+     [pins.test_forward_cycle_closed_form, pins.test_forward_mass_identity]),
+    ("back_uses_P", ox, "back_accumulate", _back_with_P,
+     [pins.test_query_exact_D_matches_power_method]),
+    ("back_levels_reversed", ox, "back_accumulate", _back_wrong_level,
+     [pins.test_query_exact_D_matches_power_method]),
+    ("diag_meeting_fraction", ox, "diag_estimate", _diag_flipped,
+     [pins.test_diag_estimate_rules]),
+    ("exact_diag_without_c", sr, "exact_diagonal", _exact_diag_no_c,
+     [pins.test_exact_diagonal_special_cases]),
+    ("levels_one_short", ox, "num_levels", _levels_off_by_one,
+     [pins.test_levels_at_paper_settings]),
+]
+
+
+@pytest.mark.parametrize("name,mod,attr,mutant,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, mod, attr, mutant, checks, monkeypatch):
+    monkeypatch.setattr(mod, attr, mutant)
+    caught = 0
+    for check in checks:
+        try:
+            check()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, f"no pin caught the mutant {name}"
