@@ -1,0 +1,205 @@
+/*
+ * exactsim.h -- C ABI of the MI355X ExactSim library (libexactsim.so).
+ *
+ * ExactSim (Wang, Wei, Yuan, Du, Wen: "Exact Single-Source SimRank
+ * Computation on Large Graphs", SIGMOD 2020) answers a single-source SimRank
+ * query: given a directed graph G, a source node u, the decay factor c and an
+ * additive error eps, return s(u, .), an estimate of column u of the SimRank
+ * matrix S of Eq. 1 (Section 1) with error at most eps for every node with
+ * probability at least 1 - 1/n (Theorem 1, Section 3.1), and optionally its
+ * top-k entries (Section 1, single-source and top-k queries).
+ *
+ * A query runs the steps of Algorithm 1 (basic ExactSim) with the sample
+ * allocation of Section 3.2:
+ *   es_forward      l-hop Personalized PageRank vectors pi^l and pi
+ *                   (Algorithm 1, lines 2-5)
+ *   es_budget       per-node walk-pair counts R(k) (Algorithm 1, lines 6-8;
+ *                   Section 3.2, "Sampling according to pi_i(k)^2")
+ *   es_walk_pairs   meeting counts M(k) of R(k) pairs of sqrt(c)-walks from
+ *                   each node (Algorithm 2)
+ *   es_diag         D^(k,k) = (R(k) - M(k)) / R(k) (Algorithm 2; exact cases
+ *                   of Algorithm 3, lines 1-4)
+ *   es_backward     s^L = 1/(1-sqrt c) sum_l (sqrt c P^T)^l D^ pi^l by the
+ *                   nested recursion of Algorithm 1, lines 9-13
+ *   es_topk         k largest entries of s (Section 1, top-k query)
+ * es_single_source runs all of them; es_batch runs many sources and many
+ * graphs at once with shared walk samples.
+ *
+ * Conventions for every call:
+ *  - Nothing is thrown across this boundary.  Every call returns an
+ *    es_status; es_last_error(ctx) holds a message for the last failure on
+ *    that context.
+ *  - "device" pointers are HIP device memory owned by the caller (for
+ *    example PyTorch tensors); "host" pointers are ordinary host memory.
+ *    Handles (es_ctx, es_graph) are owned by the library and released with
+ *    their *_destroy call.
+ *  - Work is enqueued asynchronously on the context's HIP stream.  Calls that
+ *    return values through host pointers synchronize that stream first.
+ *  - One context per host thread; calls on one context must not overlap.
+ *  - Node ids are int32 in [0, n); edge and sample counts are 64-bit.
+ *  - Results are a pure function of (graph, u, c, eps, seed, r_scale, alloc,
+ *    network weights): they do not depend on launch shapes, batch
+ *    composition or stream.  pi^l, R(k) and M(k) are bit-exact; s is float64
+ *    with summation order left to the kernels.
+ */
+#ifndef EXACTSIM_H
+#define EXACTSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct es_ctx es_ctx;
+typedef struct es_graph es_graph;
+
+typedef enum {
+  ES_OK = 0,
+  ES_EINVAL = -1,        /* an argument is out of its documented range */
+  ES_ERANGE = -2,        /* n or m exceeds the int32 index range */
+  ES_ENOMEM = -3,        /* device or host allocation failed */
+  ES_EDEVICE = -4,       /* a HIP runtime call failed */
+  ES_EOVERFLOW = -5,     /* the total sample count would reach 2^63 */
+  ES_EUNSUPPORTED = -6   /* valid request this build does not implement */
+} es_status;
+
+typedef enum {
+  ES_ALLOC_PI2 = 0,      /* R(k) = ceil(R pi(k)^2)          (Section 3.2)      */
+  ES_ALLOC_PI = 1,       /* R(k) = ceil(R pi(k))            (Algorithm 1, l.8) */
+  ES_ALLOC_LEARNED = 2   /* R(k) = ceil(R pi(k)^2 v(k)/vbar), v from the budget
+                            network; see es_mlp_load                          */
+} es_alloc;
+
+/* es_graph_from_edges flags */
+#define ES_DEDUP 1u            /* merge repeated (src, dst) pairs: Eq. 1 uses neighbour sets */
+#define ES_DROP_SELF_LOOPS 2u  /* drop (v, v) edges */
+
+typedef struct {
+  double c;                  /* decay factor, 0 < c <= 0.99 (the paper uses 0.6)            */
+  double eps;                /* additive error, 0 < eps < 1                                 */
+  uint64_t seed;             /* word 0 of the Philox key of the walk stream                 */
+  double r_scale;            /* multiplies R = 6 ln n / ((1-sqrt c)^4 eps^2); 1 = the paper */
+  int32_t alloc;             /* es_alloc                                                    */
+  int32_t exact_small_din;   /* nonzero: nodes with d_in 0 / 1 take D = 1 / 1-c, no samples  */
+  const double* d_override;  /* device [n] or NULL: use this diagonal instead of sampling   */
+} es_query_opts;
+
+typedef struct {
+  int32_t L;                 /* number of levels                                    */
+  int32_t active_nodes;      /* nodes with R(k) > 0                                 */
+  double R;                  /* total sample parameter (already times r_scale)     */
+  uint64_t pairs;            /* sum_k R(k)                                          */
+  uint64_t meets;            /* sum_k M(k)                                          */
+  float ms_forward, ms_budget, ms_walk, ms_diag, ms_backward; /* HIP-event times   */
+} es_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+es_status es_ctx_create(int device, void* hip_stream, es_ctx** out);
+es_status es_ctx_destroy(es_ctx* ctx);
+/* Block until all work enqueued on the context's stream has finished. */
+es_status es_ctx_sync(es_ctx* ctx);
+const char* es_status_str(es_status s);
+/* Message for the last failing call on ctx (never NULL; "" if none). */
+const char* es_last_error(const es_ctx* ctx);
+
+/* ---- graph -------------------------------------------------------------- */
+
+/* Build the device graph from m host edges src[e] -> dst[e].
+ * The library keeps two int32 CSR copies in device memory: rows of the
+ * out-CSR list O(v) (used by the forward pass P pi, pull form), rows of the
+ * in-CSR list I(v) in ascending id order (walks and the backward pass
+ * P^T s), plus 1/d_in(v) as float64 (Section 2: P(i,j) = 1/d_in(v_j) for
+ * v_i in I(v_j)).  Errors: ES_EINVAL (id outside [0,n), NULL pointer),
+ * ES_ERANGE (n < 1, n or m >= 2^31), ES_ENOMEM. */
+es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                              uint32_t flags, es_graph** out);
+es_status es_graph_destroy(es_graph* g);
+/* Node count and edge count after flags were applied (host outputs). */
+es_status es_graph_info(const es_graph* g, int32_t* n, int64_t* m);
+/* Copy the in-degrees (device int32 [n]) and out-degrees (device int32 [n]);
+ * either pointer may be NULL. */
+es_status es_graph_degrees(es_ctx* ctx, const es_graph* g, int32_t* din, int32_t* dout);
+
+/* ---- host constants ---------------------------------------------------- */
+
+/* L = ceil(log_{1/c}(2/eps)) of Algorithm 1, line 1, computed as the smallest
+ * L >= 0 with c^L <= eps/2 (c^L by repeated float64 multiplication). */
+es_status es_num_levels(double c, double eps, int32_t* L);
+/* R = 6 ln(n) / ((1-sqrt c)^4 eps^2) * r_scale (Algorithm 1, line 6), float64,
+ * evaluated as ((6*log(n)) / (om4*(eps*eps))) * r_scale with om = 1-sqrt(c),
+ * om4 = (om*om)*(om*om). */
+es_status es_total_samples(int32_t n, double c, double eps, double r_scale, double* R);
+
+/* ---- the steps of one query ------------------------------------------- */
+
+/* Algorithm 1, lines 2-5.  levels: device float64 [(L+1) * n], row l holds
+ * pi^l = (1-sqrt c)(sqrt c P)^l e_u; pi: device float64 [n] = sum_l pi^l
+ * summed in order of l.  Each pi^l(i) = sqrt(c) * (A * 2^-62) where A is the
+ * exact int64 sum over j in O(v_i) of round(pi^(l-1)(j)/d_in(j) * 2^62)
+ * (ties to even).  Errors: ES_EINVAL (u outside [0,n), L < 0, c outside
+ * (0, 0.99]). */
+es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
+                     double* pi);
+
+/* Algorithm 1, lines 6-8 and Section 3.2.  Rk: device uint64 [n] receives
+ * R(k) = ceil(R * (pi(k)*pi(k))) (ES_ALLOC_PI2) or ceil(R * pi(k))
+ * (ES_ALLOC_PI); 0 where pi(k) = 0 and, with exact_small_din, where
+ * d_in(k) <= 1.  ES_ALLOC_LEARNED needs weights loaded by es_mlp_load.
+ * If total is non-NULL (host), the stream is synchronized and sum_k R(k)
+ * written there.  Errors: ES_EINVAL, ES_EOVERFLOW (R + n >= 2^63). */
+es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
+                    int32_t exact_small_din, uint64_t* Rk, uint64_t* total);
+
+/* Algorithm 2.  M: device uint64 [n] receives, for every node k, the number
+ * of meeting pairs among pairs r in [r_begin(k), r_end(k)) of sqrt(c)-walk
+ * pairs from v_k (r_begin: device uint64 [n] or NULL for 0; r_end: device
+ * uint64 [n], usually R(k)).  Pair r of node k draws its randomness from
+ * Philox4x64-10 with key (seed, 0) and counter (k, r, j, 0), j = 0, 1, ...:
+ * block 0 word 0 sets the joint lifetime T (Pr[T >= t] = c^t), words 1-2
+ * move the walks at step 1, block j words 0-1 at step 2j and words 2-3 at
+ * step 2j+1; a walk moves to in-neighbour floor(w * d_in / 2^64) of its
+ * node in ascending id order, a walk on a node without in-neighbours ends
+ * the pair, and the pair meets when both walks stand on the same node after
+ * the same step t >= 1.  Because each pair is a pure function of (seed, k, r),
+ * any split of the sample ranges gives the same counts.
+ * Errors: ES_EINVAL (c outside (0, 0.99]), ES_EOVERFLOW (total >= 2^63). */
+es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                        uint64_t seed, double c, uint64_t* M);
+
+/* Algorithm 2 (estimate) and Algorithm 3, lines 1-4.  D: device float64 [n]:
+ * (R(k) - M(k)) / R(k) where R(k) > 0; with exact_small_din, 1 where
+ * d_in(k) = 0 and 1 - c where d_in(k) = 1; 1 elsewhere (pi(k) = 0, unused). */
+es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
+                  int32_t exact_small_din, double* D);
+
+/* Algorithm 1, lines 9-13.  levels as written by es_forward (L+1 rows),
+ * D: device float64 [n]; s: device float64 [n] receives
+ * s^L with s^0 = D pi^L/(1-sqrt c) and
+ * s^l(j) = sqrt(c) * (1/d_in(j)) * sum_{i in I(v_j)} s^(l-1)(i) + D(j) pi^(L-l)(j)/(1-sqrt c). */
+es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,
+                      double c, double* s);
+
+/* Whole query: every step above with library-owned workspaces.
+ * s_out: device float64 [n].  stats (host, nullable) is filled after a
+ * stream synchronization.  Errors: as the steps, plus ES_EINVAL for
+ * r_scale <= 0 or eps outside (0, 1). */
+es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_query_opts* opts,
+                           double* s_out, es_stats* stats);
+
+/* Top-k query (Section 1): the k largest s(j) over j != exclude (exclude < 0:
+ * none), in descending order, ties broken towards the smaller id.
+ * s: device float64 [n]; idx_out: device int32 [k]; val_out: device float64
+ * [k] or NULL.  Errors: ES_EINVAL (k < 1, k > n - (exclude >= 0)). */
+es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
+                  double* val_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXACTSIM_H */

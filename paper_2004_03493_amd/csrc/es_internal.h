@@ -1,0 +1,154 @@
+// Internal declarations shared by the HIP translation units of libexactsim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "exactsim.h"
+
+namespace es {
+
+// ---------------------------------------------------------------------------
+// Sparse row partition used by both SpMV directions (pull form).
+//
+// The rows of a CSR matrix are cut into work blocks, one workgroup each:
+//  * a multi-row block holds consecutive rows whose entries together fit the
+//    workgroup's LDS staging buffer (kSpmvNnz values, at most kSpmvRows rows);
+//  * a row with more than kSpmvNnz entries is a long row; it is cut into
+//    chunks of kLongChunk entries, one workgroup per chunk, whose partial
+//    sums are combined in chunk order by the last chunk to finish.
+// ---------------------------------------------------------------------------
+constexpr int kSpmvThreads = 256;
+constexpr int kSpmvNnz = 2048;
+constexpr int kSpmvRows = 512;
+constexpr int kLongChunk = 8192;
+
+struct BlockDesc {
+  int32_t row0;  // first row
+  int32_t row1;  // one past the last row; < 0: long-row chunk of long row (-row1 - 1)
+  int32_t e0;    // first entry
+  int32_t e1;    // one past the last entry
+};
+
+struct SpmvPlan {
+  BlockDesc* blocks = nullptr;  // device
+  int32_t nblocks = 0;
+  int32_t nlong = 0;
+  int32_t* long_p0 = nullptr;   // device [nlong]: first partial slot of each long row
+  int32_t* long_nch = nullptr;  // device [nlong]: chunk count of each long row
+  uint32_t* counters = nullptr; // device [nlong]: chunks finished (reset by the last one)
+  void* partials = nullptr;     // device [nslots] x 8 bytes
+  int32_t nslots = 0;
+  int32_t max_row_nnz = 0;
+};
+
+}  // namespace es
+
+struct es_graph {
+  int device = 0;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t* out_off = nullptr;  // [n+1]  rows list O(v)
+  int32_t* out_idx = nullptr;  // [m]
+  int32_t* in_off = nullptr;   // [n+1]  rows list I(v), ascending ids
+  int32_t* in_idx = nullptr;   // [m]
+  double* inv_din = nullptr;   // [n]    1/d_in(v), 0 where d_in = 0
+  es::SpmvPlan fwd;            // over the out-CSR
+  es::SpmvPlan back;           // over the in-CSR
+};
+
+struct es_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 0;
+  std::string last_error;
+  // growable device workspaces, by slot
+  std::vector<void*> ws;
+  std::vector<size_t> ws_bytes;
+  // walk lifetime thresholds for the cached decay factor
+  uint64_t* thr = nullptr;
+  int32_t tmax = 0;
+  double thr_c = -1.0;
+  hipEvent_t ev[8] = {};
+  // learned-budget network weights (device), nullptr until loaded
+  float* mlp_w = nullptr;
+};
+
+namespace es {
+
+// workspace slots
+enum Slot : int {
+  kWsLevels = 0,
+  kWsPi,
+  kWsQ0,
+  kWsQ1,
+  kWsRk,
+  kWsM,
+  kWsD,
+  kWsS0,
+  kWsS1,
+  kWsActive,
+  kWsPrefix,
+  kWsScanCnt,
+  kWsScanSum,
+  kWsTotals,
+  kWsTopk,
+  kWsMisc,
+  kWsCount
+};
+
+// device-side totals of a sample-space scan
+struct WalkTotals {
+  unsigned long long total;     // sum of sample counts
+  unsigned long long cursor;    // work-queue cursor of the walk kernel
+  unsigned long long meets;     // sum of meeting counts
+  int32_t n_active;             // nodes with a non-empty sample range
+  int32_t overflow;             // nonzero if the sum reached 2^63
+};
+
+es_status fail(es_ctx* ctx, es_status st, const char* fmt, ...);
+es_status hip_fail(es_ctx* ctx, hipError_t e, const char* what);
+void* workspace(es_ctx* ctx, int slot, size_t bytes, es_status* st);
+
+// lifetime threshold table for decay c, cached on the context
+es_status lifetime_table(es_ctx* ctx, double c);
+
+// launchers (enqueue on ctx->stream)
+es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
+                         double* pi, int64_t* q0, int64_t* q1);
+es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
+                        int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk);
+es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                       uint64_t seed, double c, uint64_t* M, WalkTotals** totals_out);
+es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
+                      int32_t exact_small_din, double* D);
+es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,
+                          double c, double* s, double* s_tmp);
+es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
+                      double* val_out);
+es_status build_plan(es_ctx* ctx, const int32_t* off_host, int32_t n, SpmvPlan* plan);
+void free_plan(SpmvPlan* plan);
+
+// host constants
+int32_t num_levels(double c, double eps);
+double total_samples(int32_t n, double c, double eps, double r_scale);
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace es
+
+#define ES_CHECK_HIP(ctx, call)                          \
+  do {                                                   \
+    hipError_t es_e_ = (call);                           \
+    if (es_e_ != hipSuccess) return es::hip_fail((ctx), es_e_, #call); \
+  } while (0)
+
+#define ES_TRY(expr)                 \
+  do {                               \
+    es_status es_s_ = (expr);        \
+    if (es_s_ != ES_OK) return es_s_; \
+  } while (0)

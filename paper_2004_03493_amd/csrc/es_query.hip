@@ -1,0 +1,182 @@
+// Public entry points for the steps of a query and the whole query.
+#include <cmath>
+#include <vector>
+
+#include "es_internal.h"
+
+namespace es {
+namespace {
+
+__global__ void degrees_kernel(int32_t n, const int32_t* __restrict__ in_off, const int32_t* __restrict__ out_off,
+                               int32_t* __restrict__ din, int32_t* __restrict__ dout) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (din) din[v] = in_off[v + 1] - in_off[v];
+  if (dout) dout[v] = out_off[v + 1] - out_off[v];
+}
+
+bool valid_c(double c) { return c > 0.0 && c <= 0.99; }
+
+}  // namespace
+}  // namespace es
+
+using namespace es;
+
+extern "C" {
+
+es_status es_graph_degrees(es_ctx* ctx, const es_graph* g, int32_t* din, int32_t* dout) {
+  if (!ctx || !g) return ES_EINVAL;
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  degrees_kernel<<<ceil_div(g->n, 256), 256, 0, ctx->stream>>>(g->n, g->in_off, g->out_off, din, dout);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels, double* pi) {
+  if (!ctx || !g) return ES_EINVAL;
+  if (u < 0 || u >= g->n) return fail(ctx, ES_EINVAL, "source %d outside [0, %d)", u, g->n);
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  if (L < 0 || !levels || !pi) return fail(ctx, ES_EINVAL, "bad L or null output");
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* q0 = (int64_t*)workspace(ctx, kWsQ0, sizeof(int64_t) * (size_t)g->n, &st);
+  if (!q0) return st;
+  auto* q1 = (int64_t*)workspace(ctx, kWsQ1, sizeof(int64_t) * (size_t)g->n, &st);
+  if (!q1) return st;
+  return launch_forward(ctx, g, u, c, L, levels, pi, q0, q1);
+}
+
+es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
+                    int32_t exact_small_din, uint64_t* Rk, uint64_t* total) {
+  if (!ctx || !g || !pi || !Rk) return ES_EINVAL;
+  if (!(R > 0.0)) return fail(ctx, ES_EINVAL, "R=%g must be positive", R);
+  if (alloc != ES_ALLOC_PI2 && alloc != ES_ALLOC_PI && alloc != ES_ALLOC_LEARNED)
+    return fail(ctx, ES_EINVAL, "unknown allocation %d", alloc);
+  if (alloc == ES_ALLOC_LEARNED)
+    return fail(ctx, ES_EINVAL, "learned allocation runs inside es_single_source after es_mlp_load");
+  // sum_k ceil(R pi(k)^2) <= R sum pi^2 + n <= R + n, since sum_k pi(k) <= 1
+  if (R + (double)g->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  ES_TRY(launch_budget(ctx, g, pi, R, alloc, exact_small_din, nullptr, 0.0, Rk));
+  if (total) {
+    std::vector<uint64_t> h((size_t)g->n);
+    ES_CHECK_HIP(ctx, hipMemcpyAsync(h.data(), Rk, 8 * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint64_t s = 0;
+    for (uint64_t v : h) s += v;
+    *total = s;
+  }
+  return ES_OK;
+}
+
+es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                        uint64_t seed, double c, uint64_t* M) {
+  if (!ctx || !g || !r_end || !M) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  WalkTotals* tot = nullptr;
+  ES_TRY(launch_walks(ctx, g, r_begin, r_end, seed, c, M, &tot));
+  WalkTotals h;
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h.overflow) return fail(ctx, ES_EOVERFLOW, "sample count reaches 2^63");
+  return ES_OK;
+}
+
+es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
+                  int32_t exact_small_din, double* D) {
+  if (!ctx || !g || !Rk || !M || !D) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  return launch_diag(ctx, g, Rk, M, c, exact_small_din, D);
+}
+
+es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D, double c,
+                      double* s) {
+  if (!ctx || !g || !levels || !D || !s) return ES_EINVAL;
+  if (L < 0) return fail(ctx, ES_EINVAL, "L=%d", L);
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* tmp = (double*)workspace(ctx, kWsS1, sizeof(double) * (size_t)g->n, &st);
+  if (!tmp) return st;
+  return launch_backward(ctx, g, levels, L, D, c, s, tmp);
+}
+
+es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_query_opts* o, double* s_out,
+                           es_stats* stats) {
+  if (!ctx || !g || !o || !s_out) return ES_EINVAL;
+  if (u < 0 || u >= g->n) return fail(ctx, ES_EINVAL, "source %d outside [0, %d)", u, g->n);
+  if (!valid_c(o->c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", o->c);
+  if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ctx, ES_EINVAL, "eps=%g outside (0, 1)", o->eps);
+  if (!(o->r_scale > 0.0)) return fail(ctx, ES_EINVAL, "r_scale=%g must be positive", o->r_scale);
+  if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI && o->alloc != ES_ALLOC_LEARNED)
+    return fail(ctx, ES_EINVAL, "unknown allocation %d", o->alloc);
+  if (o->alloc == ES_ALLOC_LEARNED && !ctx->mlp_w)
+    return fail(ctx, ES_EINVAL, "learned allocation requested but no network loaded");
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  const int32_t n = g->n;
+  const int32_t L = num_levels(o->c, o->eps);
+  const double R = total_samples(n, o->c, o->eps, o->r_scale);
+  if (!o->d_override && R + (double)n >= 9.2e18)
+    return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
+  es_status st;
+  auto* levels = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)(L + 1) * n, &st);
+  if (!levels) return st;
+  auto* pi = (double*)workspace(ctx, kWsPi, sizeof(double) * (size_t)n, &st);
+  if (!pi) return st;
+  auto* q0 = (int64_t*)workspace(ctx, kWsQ0, sizeof(int64_t) * (size_t)n, &st);
+  if (!q0) return st;
+  auto* q1 = (int64_t*)workspace(ctx, kWsQ1, sizeof(int64_t) * (size_t)n, &st);
+  if (!q1) return st;
+  auto* stmp = (double*)workspace(ctx, kWsS1, sizeof(double) * (size_t)n, &st);
+  if (!stmp) return st;
+  hipEvent_t* ev = ctx->ev;
+  ES_CHECK_HIP(ctx, hipEventRecord(ev[0], ctx->stream));
+  ES_TRY(launch_forward(ctx, g, u, o->c, L, levels, pi, q0, q1));
+  ES_CHECK_HIP(ctx, hipEventRecord(ev[1], ctx->stream));
+  const double* D = o->d_override;
+  WalkTotals* tot = nullptr;
+  if (!D) {
+    auto* Rk = (uint64_t*)workspace(ctx, kWsRk, sizeof(uint64_t) * (size_t)n, &st);
+    if (!Rk) return st;
+    auto* M = (uint64_t*)workspace(ctx, kWsM, sizeof(uint64_t) * (size_t)n, &st);
+    if (!M) return st;
+    auto* Dh = (double*)workspace(ctx, kWsD, sizeof(double) * (size_t)n, &st);
+    if (!Dh) return st;
+    if (o->alloc == ES_ALLOC_LEARNED) return fail(ctx, ES_EUNSUPPORTED, "learned allocation not built");
+    ES_TRY(launch_budget(ctx, g, pi, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[2], ctx->stream));
+    ES_TRY(launch_walks(ctx, g, nullptr, Rk, o->seed, o->c, M, &tot));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[3], ctx->stream));
+    ES_TRY(launch_diag(ctx, g, Rk, M, o->c, o->exact_small_din, Dh));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[4], ctx->stream));
+    D = Dh;
+  } else {
+    for (int e = 2; e <= 4; ++e) ES_CHECK_HIP(ctx, hipEventRecord(ev[e], ctx->stream));
+  }
+  ES_TRY(launch_backward(ctx, g, levels, L, D, o->c, s_out, stmp));
+  ES_CHECK_HIP(ctx, hipEventRecord(ev[5], ctx->stream));
+  if (stats) {
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    es_stats s{};
+    s.L = L;
+    s.R = R;
+    if (tot) {
+      WalkTotals h;
+      ES_CHECK_HIP(ctx, hipMemcpy(&h, tot, sizeof(h), hipMemcpyDeviceToHost));
+      s.pairs = h.total;
+      s.active_nodes = h.n_active;
+      s.meets = h.meets;
+    }
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_forward, ev[0], ev[1]));
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_budget, ev[1], ev[2]));
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_walk, ev[2], ev[3]));
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_diag, ev[3], ev[4]));
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_backward, ev[4], ev[5]));
+    *stats = s;
+  }
+  return ES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Level SpMV kernels of a single-source query (pull form over a CSR).
+//
+// Forward (Algorithm 1, lines 2-5):  pi^l(i) = sqrt(c) * sum_{j in O(v_i)} pi^(l-1)(j)/d_in(j),
+//   each term pre-rounded to a multiple of 2^-62 and summed exactly in int64, so the
+//   result is independent of how rows are split across lanes and workgroups.
+// Backward (Algorithm 1, lines 9-12): s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i)
+//   + D(j) pi^(L-l)(j)/(1-sqrt c), float64.
+//
+// Both are bound by HBM/Infinity-Cache traffic: the CSR index stream is read once
+// per level and the gathered operand (8 bytes per entry) comes through the caches.
+// One workgroup of 256 lanes per row block: the block's column ids are streamed
+// coalesced, the gathered operands staged in LDS, then each row is reduced by a
+// group of lanes sized to the block's average row length.
+#include "es_internal.h"
+
+namespace es {
+
+namespace {
+
+constexpr double kFix = 0x1p62;
+constexpr double kFixInv = 0x1p-62;
+
+template <class V>
+__device__ __forceinline__ V shfl_xor_v(V v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// Sum over the g lanes of a group (g a power of two <= 64, groups aligned).
+template <class V>
+__device__ __forceinline__ V group_sum(V v, int g) {
+  for (int m = g >> 1; m > 0; m >>= 1) v += shfl_xor_v(v, m);
+  return v;
+}
+
+template <class V>
+__device__ __forceinline__ V block_sum(V v, V* red) {
+  v = group_sum(v, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  V t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kSpmvThreads / 64; ++w) t += red[w];
+  return t;  // valid in thread 0
+}
+
+template <class V>
+__device__ __forceinline__ void store_partial(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class V>
+__device__ __forceinline__ V load_partial(const V* p) {
+  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct FwdGather {
+  const int64_t* __restrict__ q;
+  __device__ __forceinline__ int64_t operator()(int32_t j) const { return q[j]; }
+};
+
+struct FwdEpi {
+  double sc;
+  const double* __restrict__ inv_din;
+  double* __restrict__ pi_l;
+  int64_t* __restrict__ q_next;
+  __device__ __forceinline__ void operator()(int32_t r, int64_t acc) const {
+    const double p = sc * ((double)acc * kFixInv);
+    pi_l[r] = p;
+    q_next[r] = (int64_t)rint((p * inv_din[r]) * kFix);
+  }
+};
+
+struct BackGather {
+  const double* __restrict__ s;
+  __device__ __forceinline__ double operator()(int32_t j) const { return s[j]; }
+};
+
+struct BackEpi {
+  double sc, a;
+  const double* __restrict__ inv_din;
+  const double* __restrict__ D;
+  const double* __restrict__ pil;
+  double* __restrict__ s_next;
+  __device__ __forceinline__ void operator()(int32_t r, double acc) const {
+    s_next[r] = sc * (inv_din[r] * acc) + a * (D[r] * pil[r]);
+  }
+};
+
+template <class V, class Gather, class Epi>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc* __restrict__ blocks,
+                                                                 const int32_t* __restrict__ off,
+                                                                 const int32_t* __restrict__ idx, Gather gather,
+                                                                 Epi epi, V* __restrict__ partials,
+                                                                 const int32_t* __restrict__ long_p0,
+                                                                 const int32_t* __restrict__ long_nch,
+                                                                 uint32_t* __restrict__ counters) {
+  __shared__ V vals[kSpmvNnz];
+  __shared__ V red[kSpmvThreads / 64];
+  const BlockDesc b = blocks[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (b.row1 >= 0) {
+    const int nnz = b.e1 - b.e0;
+    constexpr int kPer = kSpmvNnz / kSpmvThreads;
+    int32_t col[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = t * kSpmvThreads + tid;
+      col[t] = e < nnz ? idx[b.e0 + e] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = t * kSpmvThreads + tid;
+      if (col[t] >= 0) vals[e] = gather(col[t]);
+    }
+    __syncthreads();
+    const int nrows = b.row1 - b.row0;
+    // lanes per row: the largest power of two <= threads / rows, at most 64
+    int g = 1;
+    while (g < 64 && g * 2 * nrows <= kSpmvThreads) g *= 2;
+    const int lane_in_g = tid & (g - 1);
+    const int groups = kSpmvThreads / g;
+    // all lanes of a group share rr, so a group's shuffles run with the whole group active
+    for (int rr = tid / g; rr < nrows; rr += groups) {
+      const int r = b.row0 + rr;
+      const int s = off[r] - b.e0, e = off[r + 1] - b.e0;
+      V acc = 0;
+      for (int k = s + lane_in_g; k < e; k += g) acc += vals[k];
+      if (g > 1) acc = group_sum(acc, g);
+      if (lane_in_g == 0) epi(r, acc);
+    }
+  } else {
+    const int lid = -b.row1 - 1;
+    const int r = b.row0;
+    V acc = 0;
+    for (int e = b.e0 + tid; e < b.e1; e += kSpmvThreads) acc += gather(idx[e]);
+    acc = block_sum(acc, red);
+    if (tid == 0) {
+      const int32_t p0 = long_p0[lid];
+      const int32_t nch = long_nch[lid];
+      const int32_t slot = p0 + (b.e0 - off[r]) / kLongChunk;
+      store_partial(&partials[slot], acc);
+      const uint32_t prev = __hip_atomic_fetch_add(&counters[lid], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == (uint32_t)(nch - 1)) {
+        V tot = 0;
+        for (int c = 0; c < nch; ++c) tot += load_partial(&partials[p0 + c]);
+        __hip_atomic_store(&counters[lid], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        epi(r, tot);
+      }
+    }
+  }
+}
+
+// pi^0 = (1 - sqrt c) e_u, q^0 = round(pi^0 / d_in * 2^62)
+__global__ void forward_init_kernel(int32_t n, int32_t u, double pi0, const double* __restrict__ inv_din,
+                                    double* __restrict__ lvl0, int64_t* __restrict__ q0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i == u) {
+    lvl0[i] = pi0;
+    q0[i] = (int64_t)rint((pi0 * inv_din[i]) * kFix);
+  } else {
+    lvl0[i] = 0.0;
+    q0[i] = 0;
+  }
+}
+
+// pi(k) = sum_{l=0}^{L} pi^l(k), added in order of l
+__global__ void sum_levels_kernel(int32_t n, int32_t L, const double* __restrict__ levels, double* __restrict__ pi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = levels[i];
+  for (int l = 1; l <= L; ++l) acc = acc + levels[(int64_t)l * n + i];
+  pi[i] = acc;
+}
+
+// s^0 = D pi^L / (1 - sqrt c)
+__global__ void backward_init_kernel(int32_t n, double a, const double* __restrict__ D,
+                                     const double* __restrict__ piL, double* __restrict__ s0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  s0[i] = a * (D[i] * piL[i]);
+}
+
+}  // namespace
+
+es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels, double* pi,
+                         int64_t* q0, int64_t* q1) {
+  const int32_t n = g->n;
+  const double sc = std::sqrt(c);
+  const int tb = 256;
+  const int nb = ceil_div(n, tb);
+  forward_init_kernel<<<nb, tb, 0, ctx->stream>>>(n, u, 1.0 - sc, g->inv_din, levels, q0);
+  int64_t* qp = q0;
+  int64_t* qn = q1;
+  for (int32_t l = 1; l <= L; ++l) {
+    FwdGather ga{qp};
+    FwdEpi ep{sc, g->inv_din, levels + (int64_t)l * n, qn};
+    if (g->fwd.nblocks > 0)
+      spmv_pull_kernel<int64_t, FwdGather, FwdEpi><<<g->fwd.nblocks, kSpmvThreads, 0, ctx->stream>>>(
+          g->fwd.blocks, g->out_off, g->out_idx, ga, ep, (int64_t*)g->fwd.partials, g->fwd.long_p0, g->fwd.long_nch,
+          g->fwd.counters);
+    std::swap(qp, qn);
+  }
+  sum_levels_kernel<<<nb, tb, 0, ctx->stream>>>(n, L, levels, pi);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D, double c,
+                          double* s, double* s_tmp) {
+  const int32_t n = g->n;
+  const double sc = std::sqrt(c);
+  const double a = 1.0 / (1.0 - sc);
+  const int tb = 256;
+  const int nb = ceil_div(n, tb);
+  // ping-pong so that level L lands in s
+  double* cur = (L % 2 == 0) ? s : s_tmp;
+  double* nxt = (L % 2 == 0) ? s_tmp : s;
+  backward_init_kernel<<<nb, tb, 0, ctx->stream>>>(n, a, D, levels + (int64_t)L * n, cur);
+  for (int32_t l = 1; l <= L; ++l) {
+    BackGather ga{cur};
+    BackEpi ep{sc, a, g->inv_din, D, levels + (int64_t)(L - l) * n, nxt};
+    if (g->back.nblocks > 0)
+      spmv_pull_kernel<double, BackGather, BackEpi><<<g->back.nblocks, kSpmvThreads, 0, ctx->stream>>>(
+          g->back.blocks, g->in_off, g->in_idx, ga, ep, (double*)g->back.partials, g->back.long_p0,
+          g->back.long_nch, g->back.counters);
+    std::swap(cur, nxt);
+  }
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+}  // namespace es

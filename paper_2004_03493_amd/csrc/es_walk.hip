@@ -1,0 +1,473 @@
+// Sample budget, sample-space scan, walk pairs and the diagonal estimate.
+//
+// Budget (Algorithm 1, lines 6-8; Section 3.2): R(k) = ceil(R * pi(k)^2).
+// Walk pairs (Algorithm 2): every node's pairs are laid end to end in one
+// 64-bit sample space [0, sum_k R(k)); a persistent grid takes fixed-size
+// chunks of it from a queue, each lane walking its own run of consecutive
+// samples.  A lane whose pair ends starts its next pair in the same loop
+// iteration, so lanes stay busy while pair lengths vary.
+// Diagonal (Algorithm 2, Algorithm 3 lines 1-4): D^(k) = (R(k) - M(k)) / R(k).
+#include <cmath>
+
+#include "es_internal.h"
+
+namespace es {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kScanThreads * kScanPer;  // nodes per scan block
+
+constexpr int kWalkThreads = 256;
+constexpr int kWalkPerLane = 64;                     // samples per lane per chunk
+constexpr uint64_t kWalkChunk = 64ull * kWalkPerLane;
+
+__global__ void budget_kernel(int32_t n, const double* __restrict__ pi, const int32_t* __restrict__ in_off,
+                              double R, int32_t alloc, int32_t exact_small_din, const float* __restrict__ vhat,
+                              double vbar_inv, uint64_t* __restrict__ Rk) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double p = pi[k];
+  const int32_t din = in_off[k + 1] - in_off[k];
+  double want;
+  if (alloc == ES_ALLOC_PI) {
+    want = R * p;
+  } else if (alloc == ES_ALLOC_LEARNED) {
+    // R * pi^2 * (v / vbar), pi^2 term first as in the pi^2 rule
+    want = R * (p * p);
+    want = want * ((double)vhat[k] * vbar_inv);
+  } else {
+    want = R * (p * p);
+  }
+  uint64_t r = (uint64_t)ceil(want);
+  if (p == 0.0) r = 0;
+  if (exact_small_din && din <= 1) r = 0;
+  Rk[k] = r;
+}
+
+__device__ __forceinline__ uint64_t sample_count(const uint64_t* r_begin, const uint64_t* r_end, int64_t k) {
+  const uint64_t e = r_end[k];
+  const uint64_t b = r_begin ? r_begin[k] : 0ull;
+  return e > b ? e - b : 0ull;
+}
+
+// Block-wide exclusive scan of (flag, value) pairs; returns totals in *tot_*.
+__device__ void block_scan2(uint32_t& f, uint64_t& v, uint32_t* tot_f, uint64_t* tot_v, uint32_t* sf,
+                            uint64_t* sv, uint32_t* ovf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // inclusive wave scan
+  uint32_t fi = f;
+  uint64_t vi = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t fo = __shfl_up(fi, d, 64);
+    const uint64_t vo = __shfl_up(vi, d, 64);
+    if (lane >= d) {
+      fi += fo;
+      const uint64_t s = vi + vo;
+      if (s < vi) *ovf = 1;
+      vi = s;
+    }
+  }
+  if (lane == 63) {
+    sf[wave] = fi;
+    sv[wave] = vi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t af = 0;
+    uint64_t av = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+      const uint32_t tf = sf[w];
+      const uint64_t tv = sv[w];
+      sf[w] = af;
+      sv[w] = av;
+      af += tf;
+      const uint64_t s = av + tv;
+      if (s < av) *ovf = 1;
+      av = s;
+    }
+    *tot_f = af;
+    *tot_v = av;
+  }
+  __syncthreads();
+  f = fi - f + sf[wave];
+  v = vi - v + sv[wave];
+}
+
+// Pass 1: per scan block, the number of nodes with samples and the sample sum.
+__global__ __launch_bounds__(kScanThreads) void scan_count_kernel(int32_t n, const uint64_t* __restrict__ r_begin,
+                                                                  const uint64_t* __restrict__ r_end,
+                                                                  uint32_t* __restrict__ bcnt,
+                                                                  uint64_t* __restrict__ bsum,
+                                                                  WalkTotals* __restrict__ tot) {
+  __shared__ uint32_t sf[kScanThreads / 64];
+  __shared__ uint64_t sv[kScanThreads / 64];
+  __shared__ uint32_t tf;
+  __shared__ uint64_t tv;
+  __shared__ uint32_t ovf;
+  if (threadIdx.x == 0) ovf = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  uint32_t f = 0;
+  uint64_t v = 0;
+  for (int t = 0; t < kScanPer; ++t) {
+    const int64_t k = base + t;
+    if (k < n) {
+      const uint64_t c = sample_count(r_begin, r_end, k);
+      f += c > 0;
+      const uint64_t s = v + c;
+      if (s < v || (s >> 63)) ovf = 1;
+      v = s;
+    }
+  }
+  block_scan2(f, v, &tf, &tv, sf, sv, &ovf);
+  if (threadIdx.x == 0) {
+    bcnt[blockIdx.x] = tf;
+    bsum[blockIdx.x] = tv;
+    if (ovf) atomicExch(&tot->overflow, 1);
+  }
+}
+
+// Pass 2 (one workgroup): exclusive scan over the scan blocks; totals.
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(int32_t nb, uint32_t* __restrict__ bcnt,
+                                                                   uint64_t* __restrict__ bsum,
+                                                                   WalkTotals* __restrict__ tot) {
+  __shared__ uint32_t sf[kScanThreads / 64];
+  __shared__ uint64_t sv[kScanThreads / 64];
+  __shared__ uint32_t tf;
+  __shared__ uint64_t tv;
+  __shared__ uint32_t ovf;
+  __shared__ uint32_t carry_f;
+  __shared__ uint64_t carry_v;
+  if (threadIdx.x == 0) {
+    ovf = 0;
+    carry_f = 0;
+    carry_v = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < nb; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    uint32_t f = i < nb ? bcnt[i] : 0;
+    uint64_t v = i < nb ? bsum[i] : 0;
+    block_scan2(f, v, &tf, &tv, sf, sv, &ovf);
+    const uint32_t cf = carry_f;
+    const uint64_t cv = carry_v;
+    if (i < nb) {
+      bcnt[i] = f + cf;
+      const uint64_t s = v + cv;
+      if (s < v) ovf = 1;
+      bsum[i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry_f = cf + tf;
+      const uint64_t s = cv + tv;
+      if (s < cv) ovf = 1;
+      carry_v = s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int32_t prior = tot->overflow;
+    const bool bad = ovf || prior || (carry_v >> 63);
+    tot->total = bad ? 0ull : carry_v;
+    tot->n_active = bad ? 0 : (int32_t)carry_f;
+    tot->overflow = bad ? 1 : 0;
+    tot->cursor = 0;
+  }
+}
+
+// Pass 3: active node list and the sample-space prefix over it.
+__global__ __launch_bounds__(kScanThreads) void scan_write_kernel(int32_t n, const uint64_t* __restrict__ r_begin,
+                                                                  const uint64_t* __restrict__ r_end,
+                                                                  const uint32_t* __restrict__ bcnt,
+                                                                  const uint64_t* __restrict__ bsum,
+                                                                  const WalkTotals* __restrict__ tot,
+                                                                  int32_t* __restrict__ active,
+                                                                  uint64_t* __restrict__ prefix) {
+  __shared__ uint32_t sf[kScanThreads / 64];
+  __shared__ uint64_t sv[kScanThreads / 64];
+  __shared__ uint32_t tf;
+  __shared__ uint64_t tv;
+  __shared__ uint32_t ovf;
+  if (tot->overflow) return;  // uniform over the grid
+  if (threadIdx.x == 0) ovf = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  uint64_t cnt[kScanPer];
+  uint32_t f = 0;
+  uint64_t v = 0;
+  for (int t = 0; t < kScanPer; ++t) {
+    const int64_t k = base + t;
+    cnt[t] = k < n ? sample_count(r_begin, r_end, k) : 0ull;
+    f += cnt[t] > 0;
+    v += cnt[t];
+  }
+  block_scan2(f, v, &tf, &tv, sf, sv, &ovf);
+  uint32_t pos = bcnt[blockIdx.x] + f;
+  uint64_t off = bsum[blockIdx.x] + v;
+  for (int t = 0; t < kScanPer; ++t) {
+    if (cnt[t] > 0) {
+      active[pos] = (int32_t)(base + t);
+      prefix[pos] = off;
+      ++pos;
+      off += cnt[t];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) prefix[tot->n_active] = tot->total;
+}
+
+__global__ void zero_u64_kernel(int64_t n, unsigned long long* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void zero_totals_kernel(WalkTotals* tot) {
+  tot->total = 0;
+  tot->cursor = 0;
+  tot->meets = 0;
+  tot->n_active = 0;
+  tot->overflow = 0;
+}
+
+// ---- Philox4x64-10 (Salmon et al., SC 2011) --------------------------------
+
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  lo = a * b;
+  hi = __umul64hi(a, b);
+}
+
+struct Words {
+  uint64_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                               uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c0, hi0, lo0);
+    mulhilo64(M1, c2, hi1, lo1);
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
+// floor(w * d / 2^64) for d < 2^32
+__device__ __forceinline__ uint32_t mulhi_index(uint64_t w, uint32_t d) {
+  const uint64_t lo = (uint64_t)(uint32_t)w * d;
+  const uint64_t hi = (w >> 32) * d;
+  return (uint32_t)((hi + (lo >> 32)) >> 32);
+}
+
+struct WalkArgs {
+  const int32_t* __restrict__ in_off;
+  const int32_t* __restrict__ in_idx;
+  const int32_t* __restrict__ active;
+  const uint64_t* __restrict__ prefix;
+  const uint64_t* __restrict__ r_begin;
+  const uint64_t* __restrict__ thr;
+  int32_t tmax;
+  WalkTotals* tot;
+  unsigned long long* __restrict__ M;
+  uint64_t seed;
+};
+
+// One step of both walks; returns 1 = met, 0 = moved without meeting, -1 = a walk is stuck.
+__device__ __forceinline__ int walk_step(const int32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
+                                         int32_t& x, int32_t& y, uint64_t wx, uint64_t wy) {
+  const int32_t ox = in_off[x], ex = in_off[x + 1];
+  const int32_t oy = in_off[y], ey = in_off[y + 1];
+  const uint32_t dx = (uint32_t)(ex - ox), dy = (uint32_t)(ey - oy);
+  if (dx == 0 || dy == 0) return -1;
+  x = in_idx[ox + mulhi_index(wx, dx)];
+  y = in_idx[oy + mulhi_index(wy, dy)];
+  return x == y ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t total = a.tot->total;
+  const int32_t nact = a.tot->n_active;
+  // meeting count held for node cnt_node, flushed when the lane moves on
+  int32_t cnt_node = -1;
+  unsigned long long cnt = 0;
+  for (;;) {
+    unsigned long long c0 = 0;
+    if (lane == 0) c0 = atomicAdd(&a.tot->cursor, (unsigned long long)kWalkChunk);
+    c0 = __shfl(c0, 0, 64);
+    if (c0 >= total) break;
+    // this lane's run of samples [i, iend)
+    uint64_t i = c0 + (uint64_t)lane * kWalkPerLane;
+    const uint64_t iend = (i + kWalkPerLane < total) ? i + kWalkPerLane : total;
+    int32_t p = 0;
+    uint64_t pbeg = 0, pend = 0;
+    if (i < iend) {
+      // last active slot whose prefix is <= i
+      int32_t lo = 0, hi = nact;  // prefix[lo] <= i < prefix[hi]
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a.prefix[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      p = lo;
+      pbeg = a.prefix[p];
+      pend = a.prefix[p + 1];
+    }
+    bool in_pair = false;
+    int32_t k = 0, x = 0, y = 0, t = 0, T = 0;
+    uint64_t r = 0;
+    for (;;) {
+      const bool start = !in_pair && i < iend;
+      const bool busy = in_pair || start;
+      if (!__any(busy)) break;
+      if (!busy) continue;
+      uint64_t blk;
+      if (start) {
+        while (i >= pend) {
+          ++p;
+          pbeg = pend;
+          pend = a.prefix[p + 1];
+        }
+        k = a.active[p];
+        r = (a.r_begin ? a.r_begin[k] : 0ull) + (i - pbeg);
+        ++i;
+        blk = 0;
+      } else {
+        blk = (uint64_t)((t + 1) >> 1);
+      }
+      const Words w = philox4x64_10((uint64_t)k, r, blk, 0ull, a.seed, 0ull);
+      int res = 0;  // 0: go on, 1: met, -1: ended without meeting
+      if (start) {
+        T = 0;
+        while (T < a.tmax && w.w0 < a.thr[T + 1]) ++T;
+        x = k;
+        y = k;
+        t = 0;
+        in_pair = true;
+        if (T == 0) {
+          res = -1;
+        } else {
+          const int st = walk_step(a.in_off, a.in_idx, x, y, w.w1, w.w2);
+          t = 1;
+          res = st != 0 ? st : (t == T ? -1 : 0);
+        }
+      } else {
+        int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
+        t += 1;
+        if (st == 0 && t < T) {
+          st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
+          t += 1;
+        }
+        res = st != 0 ? st : (t >= T ? -1 : 0);
+      }
+      if (res != 0) {
+        in_pair = false;
+        if (res > 0) {
+          if (k == cnt_node) {
+            ++cnt;
+          } else {
+            if (cnt) {
+              atomicAdd(&a.M[cnt_node], cnt);
+              atomicAdd(&a.tot->meets, cnt);
+            }
+            cnt_node = k;
+            cnt = 1;
+          }
+        }
+      }
+    }
+  }
+  if (cnt) {
+    atomicAdd(&a.M[cnt_node], cnt);
+    atomicAdd(&a.tot->meets, cnt);
+  }
+}
+
+__global__ void diag_kernel(int32_t n, const uint64_t* __restrict__ Rk, const uint64_t* __restrict__ M,
+                            const int32_t* __restrict__ in_off, double one_minus_c, int32_t exact_small_din,
+                            double* __restrict__ D) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint64_t r = Rk[k];
+  double d = 1.0;
+  if (r > 0) d = (double)(r - M[k]) / (double)r;
+  if (exact_small_din) {
+    const int32_t din = in_off[k + 1] - in_off[k];
+    if (din == 0) d = 1.0;
+    else if (din == 1) d = one_minus_c;
+  }
+  D[k] = d;
+}
+
+}  // namespace
+
+es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
+                        int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk) {
+  const int tb = 256;
+  budget_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, g->in_off, R, alloc, exact_small_din, vhat,
+                                                            vbar_inv, Rk);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                       uint64_t seed, double c, uint64_t* M, WalkTotals** totals_out) {
+  const int32_t n = g->n;
+  es_status st;
+  ES_TRY(lifetime_table(ctx, c));
+  const int nb = ceil_div(n, kScanBlock);
+  auto* tot = (WalkTotals*)workspace(ctx, kWsTotals, sizeof(WalkTotals), &st);
+  if (!tot) return st;
+  auto* bcnt = (uint32_t*)workspace(ctx, kWsScanCnt, sizeof(uint32_t) * nb, &st);
+  if (!bcnt) return st;
+  auto* bsum = (uint64_t*)workspace(ctx, kWsScanSum, sizeof(uint64_t) * nb, &st);
+  if (!bsum) return st;
+  auto* active = (int32_t*)workspace(ctx, kWsActive, sizeof(int32_t) * (size_t)n, &st);
+  if (!active) return st;
+  auto* prefix = (uint64_t*)workspace(ctx, kWsPrefix, sizeof(uint64_t) * ((size_t)n + 1), &st);
+  if (!prefix) return st;
+  zero_totals_kernel<<<1, 1, 0, ctx->stream>>>(tot);
+  zero_u64_kernel<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, (unsigned long long*)M);
+  scan_count_kernel<<<nb, kScanThreads, 0, ctx->stream>>>(n, r_begin, r_end, bcnt, bsum, tot);
+  scan_blocks_kernel<<<1, kScanThreads, 0, ctx->stream>>>(nb, bcnt, bsum, tot);
+  scan_write_kernel<<<nb, kScanThreads, 0, ctx->stream>>>(n, r_begin, r_end, bcnt, bsum, tot, active, prefix);
+  WalkArgs a;
+  a.in_off = g->in_off;
+  a.in_idx = g->in_idx;
+  a.active = active;
+  a.prefix = prefix;
+  a.r_begin = r_begin;
+  a.thr = ctx->thr;
+  a.tmax = ctx->tmax;
+  a.tot = tot;
+  a.M = (unsigned long long*)M;
+  a.seed = seed;
+  const int grid = ctx->num_cus * 8;
+  walk_pairs_kernel<<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  if (totals_out) *totals_out = tot;
+  return ES_OK;
+}
+
+es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
+                      int32_t exact_small_din, double* D) {
+  const int tb = 256;
+  diag_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, Rk, M, g->in_off, 1.0 - c, exact_small_din, D);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+}  // namespace es
