@@ -1,30 +1,45 @@
 """ExactSim single-source SimRank benchmark on one MI355X.
 
-Workload: R-MAT directed graph, n = 2^20 nodes, m = 1.6e7 edges
+Workload: R-MAT directed graph, n = 2^20 nodes, m = 1.6e7 edges,
 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), decay c = 0.6, eps = 1e-6 (L = 29),
 8 sources uniform over nodes with in-degree >= 2, each query timed on its
-own.  One step = one whole single-source query (forward PPR levels, sample
-budget, walk pairs, diagonal estimate, back-accumulation, top-500), with the
-graph already resident in HBM.
+own.  One step = one whole single-source query on the GPU (forward PPR
+levels, sample budget, walk pairs, diagonal estimate, back-accumulation,
+top-500), with the graph already resident in HBM.
 
-The paper's sample budget R = 6 ln n / ((1 - sqrt c)^4 eps^2) implies more than
-1.6e15 walk pairs per query at eps = 1e-6; a query at that budget runs for
-hours on any hardware.  The walk budget is therefore scaled by --r-scale
-(reported in the JSON line, with the measured walk rate and the projected time
-of a full-budget query).
+The paper's sample budget R = 6 ln n / ((1 - sqrt c)^4 eps^2) implies more
+than 1.6e15 walk pairs per query at eps = 1e-6, hours of work on any
+hardware.  The walk budget is scaled by --r-scale; the JSON line states it,
+the measured walk rate, and the projected time of a full-budget query.
 
-Prints ONE JSON line.
+Prints ONE JSON line on stdout (progress goes to stderr).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# MI355X: 256 compute units at 2.4 GHz, 64 lanes each; HBM3E 8 TB/s.
+CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
+PEAK_INT_TOPS = CUS * LANES * CLOCK_HZ / 1e12       # 32-bit integer VALU lane-ops
+PEAK_HBM_GBS = 8000.0
+# 32-bit integer operations of one Philox4x64-10 block, counted from its
+# definition: 10 rounds x (two 64x64->128 products of 12 ops each [4 partial
+# products, lo and hi, plus 4 carry adds], 8 xors, 4 ops of key schedule).
+OPS_PER_PHILOX_BLOCK = 10 * (2 * 12 + 8 + 4)
+# one joint walk step: two 64x32 multiply-high index maps (6 ops each)
+OPS_PER_WALK_STEP = 12
+
+WALK_SOURCE = os.path.join(ROOT, "paper_2004_03493_amd", "csrc", "es_walk.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "walk_pairs_kernel_rmat_n1048576_counters.md")
 
 
 def parse():
@@ -35,7 +50,73 @@ def parse():
     p.add_argument("--r-scale", type=float, default=1e-5)
     p.add_argument("--topk", type=int, default=500)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-pairs", type=float, default=2e8)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="after the timed region, copy 1 GiB once (reference dispatch for HBM counters)")
     return p.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per walk-kernel launch from the committed counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not h or not b or h.group(1) != source_hash(WALK_SOURCE):
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(wl, src, dst, u, r_scale, sample_pairs):
+    """The CPU oracle, untuned, on a bounded sample of one query."""
+    import numpy as np
+
+    from oracle import exactsim as ox
+    from oracle.graph import OracleGraph
+
+    og = OracleGraph(wl.n, src, dst)
+    t = time.perf_counter()
+    L = ox.num_levels(wl.c, wl.eps)
+    levels, pi = ox.forward_levels(og, u, wl.c, L)
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    R = ox.total_samples(wl.n, wl.c, wl.eps, r_scale)
+    Rk = ox.budget(pi, og.din, R)
+    t_budget = time.perf_counter() - t
+    pairs = float(Rk.sum())
+    frac = min(1.0, sample_pairs / max(pairs, 1.0))
+    Rs = np.ceil(Rk.astype(np.float64) * frac).astype(np.uint64)
+    t = time.perf_counter()
+    M = ox.walk_counts(og, Rs, wl.seed_walk, wl.c)
+    t_walk = time.perf_counter() - t
+    rate = float(Rs.sum()) / t_walk
+    t = time.perf_counter()
+    D = ox.diag_estimate(Rs, M, og.din, wl.c)
+    ox.back_accumulate(og, levels, D, wl.c)
+    t_back = time.perf_counter() - t
+    per_query = t_fwd + t_budget + pairs / rate + t_back
+    return {
+        "value": 1.0 / per_query,
+        "unit": "queries/s",
+        "cores": ox.max_threads(),
+        "kind": "oracle",
+        "sample": (f"one query (u={u}, r_scale={r_scale:g}): forward, budget, diagonal and back-accumulation "
+                   f"timed whole ({t_fwd:.2f}s, {t_budget:.2f}s, {t_back:.2f}s); walk pairs timed on "
+                   f"{int(Rs.sum())} of the query's {int(pairs)} pairs ({t_walk:.1f}s, {rate:.3g} pairs/s) "
+                   f"and scaled to the full count"),
+        "walk_pairs_per_s": rate,
+    }
 
 
 def main():
@@ -54,10 +135,10 @@ def main():
     t0 = time.time()
     src, dst = wl.graph()
     sources = wl.sources(dst)
-    print(f"# graph generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"# graph generated in {time.time() - t0:.1f}s")
     ctx = es.Context(0)
     g = es.Graph(ctx, wl.n, src, dst)
-    print(f"# graph on device: n={g.n} m={g.m}", file=sys.stderr, flush=True)
+    log(f"# graph on device: n={g.n} m={g.m}")
     s = torch.empty(g.n, dtype=torch.float64, device="cuda")
     idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
     val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
@@ -72,8 +153,7 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    stats = []
-    per_query = []
+    stats, per_query = [], []
     t_start = time.perf_counter()
     for i in range(args.steps):
         tq = time.perf_counter()
@@ -81,20 +161,33 @@ def main():
         torch.cuda.synchronize()
         per_query.append(time.perf_counter() - tq)
         stats.append(st.as_dict())
-        print(f"# step {i}: u={int(sources[i % len(sources)])} {per_query[-1]*1e3:.1f} ms pairs={st.pairs}",
-              file=sys.stderr, flush=True)
+        log(f"# step {i}: u={int(sources[i % len(sources)])} {per_query[-1] * 1e3:.1f} ms pairs={st.pairs}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     ms = elapsed / args.steps * 1e3
+    L = stats[0]["L"]
     pairs = np.array([x["pairs"] for x in stats], dtype=np.float64)
-    walk_ms = np.array([x["ms_walk"] for x in stats])
-    walk_rate = float(pairs.sum() / (walk_ms.sum() / 1e3))
-    fwd_ms = float(np.mean([x["ms_forward"] for x in stats]))
-    back_ms = float(np.mean([x["ms_backward"] for x in stats]))
-    R_full = stats[0]["R"] / args.r_scale
-    full_pairs = pairs / args.r_scale
-    other_ms = ms - float(walk_ms.mean())
-    proj_s = float(np.mean(full_pairs / walk_rate + other_ms / 1e3))
+    walk_s = np.array([x["ms_walk"] for x in stats]) / 1e3
+    walk_rate = float(pairs.sum() / walk_s.sum())
+    ops = np.array([x["philox_blocks"] * OPS_PER_PHILOX_BLOCK + x["walk_steps"] * OPS_PER_WALK_STEP
+                    for x in stats], dtype=np.float64)
+    achieved = float(ops.sum() / walk_s.sum()) / 1e12
+    traffic = measured_traffic()
+    fwd_s = np.array([x["ms_forward"] for x in stats]) / 1e3
+    back_s = np.array([x["ms_backward"] for x in stats]) / 1e3
+    fwd_bytes = L * (4.0 * g.m + 28.0 * g.n)
+    back_bytes = L * (4.0 * g.m + 44.0 * g.n)
+    other_s = ms / 1e3 - float(walk_s.mean())
+    proj_s = float(np.mean(pairs / args.r_scale / walk_rate) + other_s)
+
     out = {
         "metric": "exact single-source SimRank queries/s at eps=1e-6; walk-pairs/s; SpMV HBM GB/s",
         "value": args.steps / elapsed,
@@ -108,17 +201,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": g.n, "m": g.m, "c": c, "eps": eps, "L": stats[0]["L"],
-                   "sources": [int(x) for x in sources], "r_scale": args.r_scale, "R_paper": R_full,
-                   "topk": args.topk, "alloc": "pi2"},
+        "config": {"workload": wl.name, "n": g.n, "m": g.m, "c": c, "eps": eps, "L": L,
+                   "sources": [int(x) for x in sources], "r_scale": args.r_scale,
+                   "R": stats[0]["R"], "topk": args.topk, "alloc": "pi2"},
+        "roofline": {
+            "kernel": "walk_pairs_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
+            "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS, "traffic": traffic,
+        },
+        "roofline_spmv": {
+            "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
+            "achieved": fwd_bytes / float(fwd_s.mean()) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": fwd_bytes / float(fwd_s.mean()) / 1e9 / PEAK_HBM_GBS,
+            "backward_achieved": back_bytes / float(back_s.mean()) / 1e9,
+        },
         "walk_pairs_per_s": walk_rate,
         "pairs_per_query_mean": float(pairs.mean()),
-        "ms_forward": fwd_ms,
-        "ms_backward": back_ms,
-        "ms_walk_mean": float(walk_ms.mean()),
-        "per_query_ms": [x * 1e3 for x in per_query],
+        "ms_forward": float(fwd_s.mean() * 1e3),
+        "ms_walk": float(walk_s.mean() * 1e3),
+        "ms_backward": float(back_s.mean() * 1e3),
+        "per_query_ms": [round(x * 1e3, 3) for x in per_query],
         "projected_full_budget_s_per_query": proj_s,
     }
+    if not args.no_cpu_baseline:
+        log("# cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, src, dst, int(sources[0]), args.r_scale, args.cpu_sample_pairs)
     print(json.dumps(out), flush=True)
 
 

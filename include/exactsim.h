@@ -92,7 +92,13 @@ typedef struct {
   double R;                  /* total sample parameter (already times r_scale)     */
   uint64_t pairs;            /* sum_k R(k)                                          */
   uint64_t meets;            /* sum_k M(k)                                          */
-  float ms_forward, ms_budget, ms_walk, ms_diag, ms_backward; /* HIP-event times   */
+  uint64_t philox_blocks;    /* Philox4x64-10 blocks drawn by the walk kernel        */
+  uint64_t walk_steps;       /* joint steps taken by the walk pairs                  */
+  float ms_forward;          /* HIP-event times on the context stream: forward levels */
+  float ms_budget;           /*   budget and sample-space scan                       */
+  float ms_walk;             /*   the walk-pair kernel alone                         */
+  float ms_diag;             /*   diagonal estimate                                  */
+  float ms_backward;         /*   back-accumulation                                  */
 } es_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -52,7 +52,8 @@ class QueryOpts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("active_nodes", ctypes.c_int32), ("R", ctypes.c_double),
-                ("pairs", ctypes.c_uint64), ("meets", ctypes.c_uint64), ("ms_forward", ctypes.c_float),
+                ("pairs", ctypes.c_uint64), ("meets", ctypes.c_uint64), ("philox_blocks", ctypes.c_uint64),
+                ("walk_steps", ctypes.c_uint64), ("ms_forward", ctypes.c_float),
                 ("ms_budget", ctypes.c_float), ("ms_walk", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("ms_backward", ctypes.c_float)]
 

@@ -160,31 +160,60 @@ void free_plan(SpmvPlan* plan) {
   *plan = SpmvPlan{};
 }
 
-// Build CSR (offsets, column ids ascending within each row) of the edge keys
-// (row << 32 | col) that are already sorted: the out-CSR directly.
-static void csr_from_sorted(const std::vector<uint64_t>& keys, int32_t n, std::vector<int32_t>& off,
-                            std::vector<int32_t>& idx) {
-  off.assign((size_t)n + 1, 0);
-  idx.resize(keys.size());
-  for (size_t e = 0; e < keys.size(); ++e) {
-    off[(keys[e] >> 32) + 1]++;
-    idx[e] = (int32_t)(keys[e] & 0xffffffffu);
-  }
-  for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
-}
+// Degree-ordered relabelling and the two CSR copies under internal ids.
+// keys: edges (src << 32 | dst) in external ids, sorted ascending.
+struct HostLayout {
+  std::vector<int32_t> din_ext, dout_ext, ext_of, int_of;
+  std::vector<int32_t> out_off, out_idx, in_off, in_idx, din_int;
+  std::vector<double> inv_din;
+};
 
-// Transpose with a stable counting sort: rows of the result list their
-// columns in ascending order because the input is sorted by (row, col).
-static void csr_transpose(const std::vector<uint64_t>& keys, int32_t n, std::vector<int32_t>& off,
-                          std::vector<int32_t>& idx) {
-  off.assign((size_t)n + 1, 0);
-  idx.resize(keys.size());
-  for (size_t e = 0; e < keys.size(); ++e) off[(keys[e] & 0xffffffffu) + 1]++;
-  for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
-  std::vector<int32_t> pos(off.begin(), off.end() - 1);
-  for (size_t e = 0; e < keys.size(); ++e) {
-    const uint32_t col = (uint32_t)(keys[e] & 0xffffffffu);
-    idx[pos[col]++] = (int32_t)(keys[e] >> 32);
+static void build_layout(const std::vector<uint64_t>& keys, int32_t n, HostLayout& h) {
+  const size_t m = keys.size();
+  h.din_ext.assign(n, 0);
+  h.dout_ext.assign(n, 0);
+  for (uint64_t k : keys) {
+    h.dout_ext[k >> 32]++;
+    h.din_ext[k & 0xffffffffu]++;
+  }
+  // internal id = rank by total degree, descending, ties by external id
+  h.ext_of.resize(n);
+  for (int32_t v = 0; v < n; ++v) h.ext_of[v] = v;
+  std::stable_sort(h.ext_of.begin(), h.ext_of.end(), [&](int32_t a, int32_t b) {
+    return (int64_t)h.din_ext[a] + h.dout_ext[a] > (int64_t)h.din_ext[b] + h.dout_ext[b];
+  });
+  h.int_of.resize(n);
+  for (int32_t i = 0; i < n; ++i) h.int_of[h.ext_of[i]] = i;
+  // out-CSR: internal rows, internal columns ascending
+  h.out_off.assign((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) h.out_off[i + 1] = h.out_off[i] + h.dout_ext[h.ext_of[i]];
+  h.out_idx.resize(m);
+  {
+    std::vector<int32_t> pos(h.out_off.begin(), h.out_off.end() - 1);
+    for (uint64_t k : keys) {
+      const int32_t r = h.int_of[k >> 32];
+      h.out_idx[pos[r]++] = h.int_of[k & 0xffffffffu];
+    }
+    for (int32_t i = 0; i < n; ++i) std::sort(h.out_idx.begin() + h.out_off[i], h.out_idx.begin() + h.out_off[i + 1]);
+  }
+  // in-CSR: internal rows; a stable pass over keys sorted by external source
+  // keeps every row in ascending external source order (the walk's order)
+  h.in_off.assign((size_t)n + 1, 0);
+  h.din_int.resize(n);
+  h.inv_din.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t d = h.din_ext[h.ext_of[i]];
+    h.din_int[i] = d;
+    h.inv_din[i] = d > 0 ? 1.0 / (double)d : 0.0;
+    h.in_off[i + 1] = h.in_off[i] + d;
+  }
+  h.in_idx.resize(m);
+  {
+    std::vector<int32_t> pos(h.in_off.begin(), h.in_off.end() - 1);
+    for (uint64_t k : keys) {
+      const int32_t r = h.int_of[k & 0xffffffffu];
+      h.in_idx[pos[r]++] = h.int_of[k >> 32];
+    }
   }
 }
 
@@ -294,19 +323,18 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
   }
   if (!sorted) std::sort(keys.begin(), keys.end());
   if (flags & ES_DEDUP) keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-  std::vector<int32_t> out_off, out_idx, in_off, in_idx;
-  csr_from_sorted(keys, n, out_off, out_idx);
-  csr_transpose(keys, n, in_off, in_idx);
-  std::vector<double> inv((size_t)n);
-  for (int32_t v = 0; v < n; ++v) {
-    const int32_t d = in_off[v + 1] - in_off[v];
-    inv[v] = d > 0 ? 1.0 / (double)d : 0.0;
-  }
   es_graph* g = new (std::nothrow) es_graph();
   if (!g) return fail(ctx, ES_ENOMEM, "graph handle");
   g->device = ctx->device;
   g->n = n;
   g->m = (int64_t)keys.size();
+  HostLayout h;
+  try {
+    build_layout(keys, n, h);
+  } catch (...) {
+    delete g;
+    return fail(ctx, ES_ENOMEM, "host graph layout");
+  }
   std::vector<uint64_t>().swap(keys);
   auto up = [&](void** dptr, const void* host, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dptr, std::max<size_t>(bytes, 8));
@@ -315,17 +343,23 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
     return e;
   };
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = up((void**)&g->out_off, out_off.data(), 4 * out_off.size());
-  if (e == hipSuccess) e = up((void**)&g->out_idx, out_idx.data(), 4 * out_idx.size());
-  if (e == hipSuccess) e = up((void**)&g->in_off, in_off.data(), 4 * in_off.size());
-  if (e == hipSuccess) e = up((void**)&g->in_idx, in_idx.data(), 4 * in_idx.size());
-  if (e == hipSuccess) e = up((void**)&g->inv_din, inv.data(), 8 * inv.size());
+  if (e == hipSuccess) e = up((void**)&g->out_off, h.out_off.data(), 4 * h.out_off.size());
+  if (e == hipSuccess) e = up((void**)&g->out_idx, h.out_idx.data(), 4 * h.out_idx.size());
+  if (e == hipSuccess) e = up((void**)&g->in_off, h.in_off.data(), 4 * h.in_off.size());
+  if (e == hipSuccess) e = up((void**)&g->in_idx, h.in_idx.data(), 4 * h.in_idx.size());
+  if (e == hipSuccess) e = up((void**)&g->inv_din, h.inv_din.data(), 8 * h.inv_din.size());
+  if (e == hipSuccess) e = up((void**)&g->din_int, h.din_int.data(), 4 * h.din_int.size());
+  if (e == hipSuccess) e = up((void**)&g->din_ext, h.din_ext.data(), 4 * h.din_ext.size());
+  if (e == hipSuccess) e = up((void**)&g->dout_ext, h.dout_ext.data(), 4 * h.dout_ext.size());
+  if (e == hipSuccess) e = up((void**)&g->ext_of, h.ext_of.data(), 4 * h.ext_of.size());
+  if (e == hipSuccess) e = up((void**)&g->int_of, h.int_of.data(), 4 * h.int_of.size());
   if (e != hipSuccess) {
     es_graph_destroy(g);
     return hip_fail(ctx, e, "graph upload");
   }
-  es_status st = build_plan(ctx, out_off.data(), n, &g->fwd);
-  if (st == ES_OK) st = build_plan(ctx, in_off.data(), n, &g->back);
+  g->h_int_of = std::move(h.int_of);
+  es_status st = build_plan(ctx, h.out_off.data(), n, &g->fwd);
+  if (st == ES_OK) st = build_plan(ctx, h.in_off.data(), n, &g->back);
   if (st != ES_OK) {
     es_graph_destroy(g);
     return st;
@@ -343,6 +377,11 @@ es_status es_graph_destroy(es_graph* g) {
   hipFree(g->in_off);
   hipFree(g->in_idx);
   hipFree(g->inv_din);
+  hipFree(g->din_int);
+  hipFree(g->din_ext);
+  hipFree(g->dout_ext);
+  hipFree(g->ext_of);
+  hipFree(g->int_of);
   free_plan(&g->fwd);
   free_plan(&g->back);
   delete g;

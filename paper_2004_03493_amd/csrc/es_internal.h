@@ -48,15 +48,24 @@ struct SpmvPlan {
 
 }  // namespace es
 
+// Device graph.  Nodes are stored under internal ids: the rank of the node by
+// total degree (descending, ties by id), so that the hub entries every SpMV
+// level gathers share few cache lines.  Callers only ever see external ids.
 struct es_graph {
   int device = 0;
   int32_t n = 0;
   int64_t m = 0;
-  int32_t* out_off = nullptr;  // [n+1]  rows list O(v)
+  int32_t* out_off = nullptr;  // [n+1]  internal rows list O(v) (internal ids, ascending)
   int32_t* out_idx = nullptr;  // [m]
-  int32_t* in_off = nullptr;   // [n+1]  rows list I(v), ascending ids
+  int32_t* in_off = nullptr;   // [n+1]  internal rows list I(v): internal ids in ascending EXTERNAL id order
   int32_t* in_idx = nullptr;   // [m]
-  double* inv_din = nullptr;   // [n]    1/d_in(v), 0 where d_in = 0
+  double* inv_din = nullptr;   // [n]    1/d_in(v) by internal id, 0 where d_in = 0
+  int32_t* din_int = nullptr;  // [n]    d_in by internal id
+  int32_t* din_ext = nullptr;  // [n]    d_in by external id
+  int32_t* dout_ext = nullptr; // [n]    d_out by external id
+  int32_t* ext_of = nullptr;   // [n]    internal id -> external id
+  int32_t* int_of = nullptr;   // [n]    external id -> internal id
+  std::vector<int32_t> h_int_of;
   es::SpmvPlan fwd;            // over the out-CSR
   es::SpmvPlan back;           // over the in-CSR
 };
@@ -74,6 +83,7 @@ struct es_ctx {
   int32_t tmax = 0;
   double thr_c = -1.0;
   hipEvent_t ev[8] = {};
+  hipEvent_t ev_walk_begin = nullptr;  // set while a query records stage times
   // learned-budget network weights (device), nullptr until loaded
   float* mlp_w = nullptr;
 };
@@ -106,6 +116,8 @@ struct WalkTotals {
   unsigned long long total;     // sum of sample counts
   unsigned long long cursor;    // work-queue cursor of the walk kernel
   unsigned long long meets;     // sum of meeting counts
+  unsigned long long blocks;    // Philox4x64-10 blocks drawn
+  unsigned long long steps;     // joint walk steps taken
   int32_t n_active;             // nodes with a non-empty sample range
   int32_t overflow;             // nonzero if the sum reached 2^63
 };
@@ -120,12 +132,16 @@ es_status lifetime_table(es_ctx* ctx, double c);
 // launchers (enqueue on ctx->stream)
 es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
                          double* pi, int64_t* q0, int64_t* q1);
-es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
-                        int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk);
+es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const int32_t* din, double R,
+                        int32_t alloc, int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk);
+// Walk pairs over sample counts indexed by internal ids (external_counts = false)
+// or by external ids (external_counts = true); M is indexed like the counts.
 es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
-                       uint64_t seed, double c, uint64_t* M, WalkTotals** totals_out);
-es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
-                      int32_t exact_small_din, double* D);
+                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out);
+es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
+                      double c, int32_t exact_small_din, double* D);
+// dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1
+es_status launch_permute_f64(es_ctx* ctx, int32_t n, int32_t rows, const double* src, const int32_t* map, double* dst);
 es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,
                           double c, double* s, double* s_tmp);
 es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,

@@ -7,17 +7,30 @@
 namespace es {
 namespace {
 
-__global__ void degrees_kernel(int32_t n, const int32_t* __restrict__ in_off, const int32_t* __restrict__ out_off,
-                               int32_t* __restrict__ din, int32_t* __restrict__ dout) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  if (din) din[v] = in_off[v + 1] - in_off[v];
-  if (dout) dout[v] = out_off[v + 1] - out_off[v];
+__global__ void permute_rows_kernel(int32_t n, const double* __restrict__ src, const int32_t* __restrict__ map,
+                                    double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = (int64_t)blockIdx.y * n;
+  dst[row + i] = src[row + map[i]];
 }
 
 bool valid_c(double c) { return c > 0.0 && c <= 0.99; }
 
 }  // namespace
+
+es_status launch_permute_f64(es_ctx* ctx, int32_t n, int32_t rows, const double* src, const int32_t* map,
+                             double* dst) {
+  if (n <= 0 || rows <= 0) return ES_OK;
+  for (int32_t r0 = 0; r0 < rows; r0 += 65535) {
+    const int32_t nr = std::min<int32_t>(65535, rows - r0);
+    dim3 grid(ceil_div(n, 256), nr);
+    permute_rows_kernel<<<grid, 256, 0, ctx->stream>>>(n, src + (int64_t)r0 * n, map, dst + (int64_t)r0 * n);
+  }
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
 }  // namespace es
 
 using namespace es;
@@ -27,8 +40,9 @@ extern "C" {
 es_status es_graph_degrees(es_ctx* ctx, const es_graph* g, int32_t* din, int32_t* dout) {
   if (!ctx || !g) return ES_EINVAL;
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  degrees_kernel<<<ceil_div(g->n, 256), 256, 0, ctx->stream>>>(g->n, g->in_off, g->out_off, din, dout);
-  ES_CHECK_HIP(ctx, hipGetLastError());
+  if (din) ES_CHECK_HIP(ctx, hipMemcpyAsync(din, g->din_ext, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, ctx->stream));
+  if (dout)
+    ES_CHECK_HIP(ctx, hipMemcpyAsync(dout, g->dout_ext, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, ctx->stream));
   return ES_OK;
 }
 
@@ -39,11 +53,18 @@ es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_
   if (L < 0 || !levels || !pi) return fail(ctx, ES_EINVAL, "bad L or null output");
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   es_status st;
-  auto* q0 = (int64_t*)workspace(ctx, kWsQ0, sizeof(int64_t) * (size_t)g->n, &st);
+  const int32_t n = g->n;
+  auto* q0 = (int64_t*)workspace(ctx, kWsQ0, sizeof(int64_t) * (size_t)n, &st);
   if (!q0) return st;
-  auto* q1 = (int64_t*)workspace(ctx, kWsQ1, sizeof(int64_t) * (size_t)g->n, &st);
+  auto* q1 = (int64_t*)workspace(ctx, kWsQ1, sizeof(int64_t) * (size_t)n, &st);
   if (!q1) return st;
-  return launch_forward(ctx, g, u, c, L, levels, pi, q0, q1);
+  auto* lv = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)(L + 1) * n, &st);
+  if (!lv) return st;
+  auto* pii = (double*)workspace(ctx, kWsPi, sizeof(double) * (size_t)n, &st);
+  if (!pii) return st;
+  ES_TRY(launch_forward(ctx, g, g->h_int_of[u], c, L, lv, pii, q0, q1));
+  ES_TRY(launch_permute_f64(ctx, n, L + 1, lv, g->int_of, levels));
+  return launch_permute_f64(ctx, n, 1, pii, g->int_of, pi);
 }
 
 es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
@@ -57,7 +78,7 @@ es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, 
   // sum_k ceil(R pi(k)^2) <= R sum pi^2 + n <= R + n, since sum_k pi(k) <= 1
   if (R + (double)g->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  ES_TRY(launch_budget(ctx, g, pi, R, alloc, exact_small_din, nullptr, 0.0, Rk));
+  ES_TRY(launch_budget(ctx, g, pi, g->din_ext, R, alloc, exact_small_din, nullptr, 0.0, Rk));
   if (total) {
     std::vector<uint64_t> h((size_t)g->n);
     ES_CHECK_HIP(ctx, hipMemcpyAsync(h.data(), Rk, 8 * h.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -75,7 +96,7 @@ es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin,
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   WalkTotals* tot = nullptr;
-  ES_TRY(launch_walks(ctx, g, r_begin, r_end, seed, c, M, &tot));
+  ES_TRY(launch_walks(ctx, g, r_begin, r_end, seed, c, M, true, &tot));
   WalkTotals h;
   ES_CHECK_HIP(ctx, hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -88,7 +109,7 @@ es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint
   if (!ctx || !g || !Rk || !M || !D) return ES_EINVAL;
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  return launch_diag(ctx, g, Rk, M, c, exact_small_din, D);
+  return launch_diag(ctx, g, Rk, M, g->din_ext, c, exact_small_din, D);
 }
 
 es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D, double c,
@@ -98,9 +119,19 @@ es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int3
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   es_status st;
-  auto* tmp = (double*)workspace(ctx, kWsS1, sizeof(double) * (size_t)g->n, &st);
+  const int32_t n = g->n;
+  auto* lv = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)(L + 1) * n, &st);
+  if (!lv) return st;
+  auto* Di = (double*)workspace(ctx, kWsD, sizeof(double) * (size_t)n, &st);
+  if (!Di) return st;
+  auto* s0 = (double*)workspace(ctx, kWsS0, sizeof(double) * (size_t)n, &st);
+  if (!s0) return st;
+  auto* tmp = (double*)workspace(ctx, kWsS1, sizeof(double) * (size_t)n, &st);
   if (!tmp) return st;
-  return launch_backward(ctx, g, levels, L, D, c, s, tmp);
+  ES_TRY(launch_permute_f64(ctx, n, L + 1, levels, g->ext_of, lv));
+  ES_TRY(launch_permute_f64(ctx, n, 1, D, g->ext_of, Di));
+  ES_TRY(launch_backward(ctx, g, lv, L, Di, c, s0, tmp));
+  return launch_permute_f64(ctx, n, 1, s0, g->int_of, s);
 }
 
 es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_query_opts* o, double* s_out,
@@ -131,31 +162,37 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   if (!q1) return st;
   auto* stmp = (double*)workspace(ctx, kWsS1, sizeof(double) * (size_t)n, &st);
   if (!stmp) return st;
+  auto* sint = (double*)workspace(ctx, kWsS0, sizeof(double) * (size_t)n, &st);
+  if (!sint) return st;
+  auto* Dh = (double*)workspace(ctx, kWsD, sizeof(double) * (size_t)n, &st);
+  if (!Dh) return st;
   hipEvent_t* ev = ctx->ev;
   ES_CHECK_HIP(ctx, hipEventRecord(ev[0], ctx->stream));
-  ES_TRY(launch_forward(ctx, g, u, o->c, L, levels, pi, q0, q1));
+  ES_TRY(launch_forward(ctx, g, g->h_int_of[u], o->c, L, levels, pi, q0, q1));
   ES_CHECK_HIP(ctx, hipEventRecord(ev[1], ctx->stream));
-  const double* D = o->d_override;
   WalkTotals* tot = nullptr;
-  if (!D) {
+  if (!o->d_override) {
     auto* Rk = (uint64_t*)workspace(ctx, kWsRk, sizeof(uint64_t) * (size_t)n, &st);
     if (!Rk) return st;
     auto* M = (uint64_t*)workspace(ctx, kWsM, sizeof(uint64_t) * (size_t)n, &st);
     if (!M) return st;
-    auto* Dh = (double*)workspace(ctx, kWsD, sizeof(double) * (size_t)n, &st);
-    if (!Dh) return st;
     if (o->alloc == ES_ALLOC_LEARNED) return fail(ctx, ES_EUNSUPPORTED, "learned allocation not built");
-    ES_TRY(launch_budget(ctx, g, pi, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
-    ES_CHECK_HIP(ctx, hipEventRecord(ev[2], ctx->stream));
-    ES_TRY(launch_walks(ctx, g, nullptr, Rk, o->seed, o->c, M, &tot));
+    ES_TRY(launch_budget(ctx, g, pi, g->din_int, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
+    ctx->ev_walk_begin = ev[2];  // recorded between the sample-space scan and the walk kernel
+    const es_status ws = launch_walks(ctx, g, nullptr, Rk, o->seed, o->c, M, false, &tot);
+    ctx->ev_walk_begin = nullptr;
+    ES_TRY(ws);
     ES_CHECK_HIP(ctx, hipEventRecord(ev[3], ctx->stream));
-    ES_TRY(launch_diag(ctx, g, Rk, M, o->c, o->exact_small_din, Dh));
+    ES_TRY(launch_diag(ctx, g, Rk, M, g->din_int, o->c, o->exact_small_din, Dh));
     ES_CHECK_HIP(ctx, hipEventRecord(ev[4], ctx->stream));
-    D = Dh;
   } else {
-    for (int e = 2; e <= 4; ++e) ES_CHECK_HIP(ctx, hipEventRecord(ev[e], ctx->stream));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[2], ctx->stream));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[3], ctx->stream));
+    ES_TRY(launch_permute_f64(ctx, n, 1, o->d_override, g->ext_of, Dh));
+    ES_CHECK_HIP(ctx, hipEventRecord(ev[4], ctx->stream));
   }
-  ES_TRY(launch_backward(ctx, g, levels, L, D, o->c, s_out, stmp));
+  ES_TRY(launch_backward(ctx, g, levels, L, Dh, o->c, sint, stmp));
+  ES_TRY(launch_permute_f64(ctx, n, 1, sint, g->int_of, s_out));
   ES_CHECK_HIP(ctx, hipEventRecord(ev[5], ctx->stream));
   if (stats) {
     ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -168,6 +205,8 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
       s.pairs = h.total;
       s.active_nodes = h.n_active;
       s.meets = h.meets;
+      s.philox_blocks = h.blocks;
+      s.walk_steps = h.steps;
     }
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_forward, ev[0], ev[1]));
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_budget, ev[1], ev[2]));

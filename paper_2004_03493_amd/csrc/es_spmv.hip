@@ -101,16 +101,20 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
   if (b.row1 >= 0) {
     const int nnz = b.e1 - b.e0;
     constexpr int kPer = kSpmvNnz / kSpmvThreads;
-    int32_t col[kPer];
+    if (nnz > 0) {
+      // branch-free so that all kPer index loads, then all kPer gathers, are in flight at once;
+      // lanes past the end re-read the block's last entry and do not store it
+      int32_t col[kPer];
 #pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int e = t * kSpmvThreads + tid;
-      col[t] = e < nnz ? idx[b.e0 + e] : -1;
-    }
+      for (int t = 0; t < kPer; ++t) col[t] = idx[b.e0 + min(t * kSpmvThreads + tid, nnz - 1)];
+      V v[kPer];
 #pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int e = t * kSpmvThreads + tid;
-      if (col[t] >= 0) vals[e] = gather(col[t]);
+      for (int t = 0; t < kPer; ++t) v[t] = gather(col[t]);
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int e = t * kSpmvThreads + tid;
+        if (e < nnz) vals[e] = v[t];
+      }
     }
     __syncthreads();
     const int nrows = b.row1 - b.row0;
@@ -132,7 +136,18 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
     const int lid = -b.row1 - 1;
     const int r = b.row0;
     V acc = 0;
-    for (int e = b.e0 + tid; e < b.e1; e += kSpmvThreads) acc += gather(idx[e]);
+    constexpr int kUnroll = 8;
+    for (int base = b.e0; base < b.e1; base += kUnroll * kSpmvThreads) {
+      int32_t col[kUnroll];
+#pragma unroll
+      for (int t = 0; t < kUnroll; ++t) col[t] = idx[min(base + t * kSpmvThreads + tid, b.e1 - 1)];
+      V v[kUnroll];
+#pragma unroll
+      for (int t = 0; t < kUnroll; ++t) v[t] = gather(col[t]);
+#pragma unroll
+      for (int t = 0; t < kUnroll; ++t)
+        if (base + t * kSpmvThreads + tid < b.e1) acc += v[t];
+    }
     acc = block_sum(acc, red);
     if (tid == 0) {
       const int32_t p0 = long_p0[lid];

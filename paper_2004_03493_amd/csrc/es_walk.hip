@@ -23,13 +23,13 @@ constexpr int kWalkThreads = 256;
 constexpr int kWalkPerLane = 64;                     // samples per lane per chunk
 constexpr uint64_t kWalkChunk = 64ull * kWalkPerLane;
 
-__global__ void budget_kernel(int32_t n, const double* __restrict__ pi, const int32_t* __restrict__ in_off,
+__global__ void budget_kernel(int32_t n, const double* __restrict__ pi, const int32_t* __restrict__ din_arr,
                               double R, int32_t alloc, int32_t exact_small_din, const float* __restrict__ vhat,
                               double vbar_inv, uint64_t* __restrict__ Rk) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double p = pi[k];
-  const int32_t din = in_off[k + 1] - in_off[k];
+  const int32_t din = din_arr[k];
   double want;
   if (alloc == ES_ALLOC_PI) {
     want = R * p;
@@ -227,6 +227,8 @@ __global__ void zero_totals_kernel(WalkTotals* tot) {
   tot->total = 0;
   tot->cursor = 0;
   tot->meets = 0;
+  tot->blocks = 0;
+  tot->steps = 0;
   tot->n_active = 0;
   tot->overflow = 0;
 }
@@ -278,6 +280,8 @@ struct WalkArgs {
   const int32_t* __restrict__ active;
   const uint64_t* __restrict__ prefix;
   const uint64_t* __restrict__ r_begin;
+  const int32_t* __restrict__ to_graph;   // count index -> internal id (NULL: identity)
+  const int32_t* __restrict__ to_stream;  // count index -> external id (NULL: identity)
   const uint64_t* __restrict__ thr;
   int32_t tmax;
   WalkTotals* tot;
@@ -304,6 +308,7 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
   // meeting count held for node cnt_node, flushed when the lane moves on
   int32_t cnt_node = -1;
   unsigned long long cnt = 0;
+  unsigned long long nblocks = 0, nsteps = 0;  // work counters for the roofline
   for (;;) {
     unsigned long long c0 = 0;
     if (lane == 0) c0 = atomicAdd(&a.tot->cursor, (unsigned long long)kWalkChunk);
@@ -327,8 +332,8 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
       pend = a.prefix[p + 1];
     }
     bool in_pair = false;
-    int32_t k = 0, x = 0, y = 0, t = 0, T = 0;
-    uint64_t r = 0;
+    int32_t k = 0, x = 0, y = 0, t = 0, T = 0, kg = 0;
+    uint64_t r = 0, kc = 0;
     for (;;) {
       const bool start = !in_pair && i < iend;
       const bool busy = in_pair || start;
@@ -343,33 +348,39 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
         }
         k = a.active[p];
         r = (a.r_begin ? a.r_begin[k] : 0ull) + (i - pbeg);
+        kg = a.to_graph ? a.to_graph[k] : k;
+        kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
         ++i;
         blk = 0;
       } else {
         blk = (uint64_t)((t + 1) >> 1);
       }
-      const Words w = philox4x64_10((uint64_t)k, r, blk, 0ull, a.seed, 0ull);
+      const Words w = philox4x64_10(kc, r, blk, 0ull, a.seed, 0ull);
+      ++nblocks;
       int res = 0;  // 0: go on, 1: met, -1: ended without meeting
       if (start) {
         T = 0;
         while (T < a.tmax && w.w0 < a.thr[T + 1]) ++T;
-        x = k;
-        y = k;
+        x = kg;
+        y = kg;
         t = 0;
         in_pair = true;
         if (T == 0) {
           res = -1;
         } else {
           const int st = walk_step(a.in_off, a.in_idx, x, y, w.w1, w.w2);
+          ++nsteps;
           t = 1;
           res = st != 0 ? st : (t == T ? -1 : 0);
         }
       } else {
         int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
         t += 1;
+        ++nsteps;
         if (st == 0 && t < T) {
           st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
           t += 1;
+          ++nsteps;
         }
         res = st != 0 ? st : (t >= T ? -1 : 0);
       }
@@ -394,10 +405,19 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
     atomicAdd(&a.M[cnt_node], cnt);
     atomicAdd(&a.tot->meets, cnt);
   }
+  // one atomic per wave for the work counters
+  for (int m = 32; m > 0; m >>= 1) {
+    nblocks += __shfl_xor(nblocks, m, 64);
+    nsteps += __shfl_xor(nsteps, m, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(&a.tot->blocks, nblocks);
+    atomicAdd(&a.tot->steps, nsteps);
+  }
 }
 
 __global__ void diag_kernel(int32_t n, const uint64_t* __restrict__ Rk, const uint64_t* __restrict__ M,
-                            const int32_t* __restrict__ in_off, double one_minus_c, int32_t exact_small_din,
+                            const int32_t* __restrict__ din_arr, double one_minus_c, int32_t exact_small_din,
                             double* __restrict__ D) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -405,7 +425,7 @@ __global__ void diag_kernel(int32_t n, const uint64_t* __restrict__ Rk, const ui
   double d = 1.0;
   if (r > 0) d = (double)(r - M[k]) / (double)r;
   if (exact_small_din) {
-    const int32_t din = in_off[k + 1] - in_off[k];
+    const int32_t din = din_arr[k];
     if (din == 0) d = 1.0;
     else if (din == 1) d = one_minus_c;
   }
@@ -414,17 +434,17 @@ __global__ void diag_kernel(int32_t n, const uint64_t* __restrict__ Rk, const ui
 
 }  // namespace
 
-es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
-                        int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk) {
+es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const int32_t* din, double R,
+                        int32_t alloc, int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk) {
   const int tb = 256;
-  budget_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, g->in_off, R, alloc, exact_small_din, vhat,
+  budget_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, din, R, alloc, exact_small_din, vhat,
                                                             vbar_inv, Rk);
   ES_CHECK_HIP(ctx, hipGetLastError());
   return ES_OK;
 }
 
 es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
-                       uint64_t seed, double c, uint64_t* M, WalkTotals** totals_out) {
+                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out) {
   const int32_t n = g->n;
   es_status st;
   ES_TRY(lifetime_table(ctx, c));
@@ -450,22 +470,25 @@ es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, 
   a.active = active;
   a.prefix = prefix;
   a.r_begin = r_begin;
+  a.to_graph = external_counts ? g->int_of : nullptr;
+  a.to_stream = external_counts ? nullptr : g->ext_of;
   a.thr = ctx->thr;
   a.tmax = ctx->tmax;
   a.tot = tot;
   a.M = (unsigned long long*)M;
   a.seed = seed;
   const int grid = ctx->num_cus * 8;
+  if (ctx->ev_walk_begin) ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev_walk_begin, ctx->stream));
   walk_pairs_kernel<<<grid, kWalkThreads, 0, ctx->stream>>>(a);
   ES_CHECK_HIP(ctx, hipGetLastError());
   if (totals_out) *totals_out = tot;
   return ES_OK;
 }
 
-es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
-                      int32_t exact_small_din, double* D) {
+es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
+                      double c, int32_t exact_small_din, double* D) {
   const int tb = 256;
-  diag_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, Rk, M, g->in_off, 1.0 - c, exact_small_din, D);
+  diag_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, Rk, M, din, 1.0 - c, exact_small_din, D);
   ES_CHECK_HIP(ctx, hipGetLastError());
   return ES_OK;
 }
