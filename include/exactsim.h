@@ -90,7 +90,8 @@ typedef struct {
   int32_t L;                 /* number of levels                                    */
   int32_t active_nodes;      /* nodes with R(k) > 0                                 */
   double R;                  /* total sample parameter (already times r_scale)     */
-  uint64_t pairs;            /* sum_k R(k)                                          */
+  uint64_t pairs;            /* walk pairs simulated (sum_k R(k); a batch shares them) */
+  uint64_t pairs_requested;  /* sum over queries of sum_k R(k)                       */
   uint64_t meets;            /* sum_k M(k)                                          */
   uint64_t philox_blocks;    /* Philox4x64-10 blocks drawn by the walk kernel        */
   uint64_t walk_steps;       /* joint steps taken by the walk pairs                  */
@@ -203,6 +204,41 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
  * [k] or NULL.  Errors: ES_EINVAL (k < 1, k > n - (exclude >= 0)). */
 es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                   double* val_out);
+
+/* ---- batches ------------------------------------------------------------ */
+
+typedef struct {
+  int32_t use_hip_graph;  /* nonzero: capture the batch in a hipGraph and replay it when the same
+                             plan (graphs, block widths, options, workspace) comes again          */
+  int32_t autotune;       /* nonzero: on first use of a (graph, block width) time the candidate
+                             tilings of the level SpMM and keep the fastest                        */
+  int32_t force_width;    /* 0, or lanes per row of the level SpMM (8, 16, 32 or 64, >= block width) */
+  int32_t force_rows;     /* 0, or entries per lane per tile (rows per wave pass)                   */
+} es_batch_opts;
+
+/* Many single-source queries at once (same c, eps, seed, r_scale, alloc):
+ * query q asks for s(sources[q], .) on graphs[graph_of_query[q]].  Queries of
+ * one graph are grouped in source blocks of at most 64; each block runs the
+ * level SpMV as one SpMM over its sources (Algorithm 1, lines 2-5 and 9-12 for
+ * every source at once) in a single fused launch per level across all blocks
+ * and graphs, and the blocks draw shared walk samples: node k of a block
+ * simulates max_b R_b(k) pairs once and source b uses pairs r < R_b(k)
+ * (Algorithm 2), so every source's counts, and therefore its D^ and s, are the
+ * ones its own single-source query gives.
+ * graphs: host array [ngraphs]; graph_of_query, sources: host int32 [nq];
+ * s_out: host array [nq] of device float64 [n of that graph] outputs.
+ * bopts may be NULL (defaults: no hipGraph, autotune on).
+ * stats (nullable): pairs = pairs simulated, pairs_requested = sum over queries,
+ * meets = sum over queries of sum_k M(k); times are 0 except ms_walk (all walks).
+ * Errors: as es_single_source; ES_EINVAL for a bad graph index, source or
+ * width; ES_EUNSUPPORTED for d_override or the learned allocation. */
+es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, const int32_t* graph_of_query,
+                   const int32_t* sources, int32_t nq, const es_query_opts* opts, const es_batch_opts* bopts,
+                   double* const* s_out, es_stats* stats);
+
+/* The tiling the autotuner chose for graph g and source-block width B
+ * (host outputs; 0 if not tuned yet). */
+es_status es_batch_tuning(const es_graph* g, int32_t B, int32_t* width, int32_t* rows);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ SYMBOLS = (
     "es_ctx_create", "es_ctx_destroy", "es_ctx_sync", "es_status_str", "es_last_error",
     "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_degrees",
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
-    "es_backward", "es_single_source", "es_topk",
+    "es_backward", "es_single_source", "es_topk", "es_batch", "es_batch_tuning",
 )
 
 
@@ -50,9 +50,15 @@ class QueryOpts(ctypes.Structure):
                 ("d_override", ctypes.c_void_p)]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("use_hip_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("force_width", ctypes.c_int32), ("force_rows", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("active_nodes", ctypes.c_int32), ("R", ctypes.c_double),
-                ("pairs", ctypes.c_uint64), ("meets", ctypes.c_uint64), ("philox_blocks", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64), ("pairs_requested", ctypes.c_uint64), ("meets", ctypes.c_uint64),
+                ("philox_blocks", ctypes.c_uint64),
                 ("walk_steps", ctypes.c_uint64), ("ms_forward", ctypes.c_float),
                 ("ms_budget", ctypes.c_float), ("ms_walk", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("ms_backward", ctypes.c_float)]
@@ -93,6 +99,9 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_backward": [P, P, P, i32, P, dbl, P],
         "es_single_source": [P, P, i32, ctypes.POINTER(QueryOpts), P, ctypes.POINTER(Stats)],
         "es_topk": [P, P, i32, i32, i32, P, P],
+        "es_batch": [P, P, i32, P, P, i32, ctypes.POINTER(QueryOpts), ctypes.POINTER(BatchOpts), P,
+                     ctypes.POINTER(Stats)],
+        "es_batch_tuning": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -266,3 +275,34 @@ def es_topk(ctx: Context, s, n: int, exclude: int, k: int, idx_out, val_out=None
     _check(load_library().es_topk(ctx.handle, _ptr(s, torch.float64, n, "s"), n, exclude, k,
                                   _ptr(idx_out, torch.int32, k, "idx_out"),
                                   _ptr(val_out, torch.float64, k, "val_out")), ctx)
+
+
+def es_batch(ctx: Context, graphs, graph_of_query, sources, opts: QueryOpts, outs, use_hip_graph: bool = False,
+             autotune: bool = True, force_width: int = 0, force_rows: int = 0, want_stats: bool = True):
+    """Batched queries: graphs is a list of Graph, outs a list of float64 device tensors."""
+    import numpy as np
+    lib = load_library()
+    nq = len(sources)
+    if len(graph_of_query) != nq or len(outs) != nq:
+        raise ValueError("graph_of_query, sources and outs must have one entry per query")
+    gh = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+    goq = np.ascontiguousarray(graph_of_query, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    ptrs = []
+    for q in range(nq):
+        gi = int(goq[q])
+        n = graphs[gi].n if 0 <= gi < len(graphs) else None  # a bad index is the library's to report
+        ptrs.append(_ptr(outs[q], torch.float64, n, f"outs[{q}]").value)
+    op = (ctypes.c_void_p * nq)(*ptrs)
+    bo = BatchOpts(int(use_hip_graph), int(autotune), int(force_width), int(force_rows))
+    st = Stats()
+    _check(lib.es_batch(ctx.handle, gh, len(graphs), goq.ctypes.data, src.ctypes.data, nq, ctypes.byref(opts),
+                        ctypes.byref(bo), op, ctypes.byref(st) if want_stats else None), ctx)
+    return st if want_stats else None
+
+
+def es_batch_tuning(g: Graph, B: int):
+    w = ctypes.c_int32()
+    r = ctypes.c_int32()
+    _check(load_library().es_batch_tuning(g.handle, B, ctypes.byref(w), ctypes.byref(r)))
+    return w.value, r.value

@@ -1,0 +1,887 @@
+// Batched queries: blocks of up to 64 sources on one or more graphs.
+//
+// Per (node, source) arrays of every block live in flat buffers, node-major
+// within a block (element base + r * B + b), so that one SpMM edge gathers the
+// B contiguous values of a row.  The level SpMM (Algorithm 1, lines 2-5 and
+// 9-12 for all sources at once) runs as one launch per level over a tile list
+// that covers every block of every graph: a tile is a run of rows of one block
+// handled by one wave, whose 64 lanes form 64/W groups of W lanes; lane b of a
+// group owns source column b.  Rows longer than kLongRow are cut into chunks
+// that whole waves sum and add atomically into per-row accumulators, finished
+// by a small launch after the level.  The walk phase shares samples inside a
+// block: node k simulates max_b R_b(k) pairs and the meetings are bucketed by
+// the block's sorted per-source counts, so source b sees exactly the meetings of
+// its own pairs r < R_b(k).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "es_internal.h"
+
+namespace es {
+
+namespace {
+
+constexpr int kBatchMaxB = 64;
+constexpr int kSpmmThreads = 256;  // four independent waves
+constexpr int kLongRow = 1024;
+constexpr double kFix = 0x1p62;
+constexpr double kFixInv = 0x1p-62;
+
+struct BEntry {
+  const int32_t* out_off;
+  const int32_t* out_idx;
+  const int32_t* in_off;
+  const int32_t* in_idx;
+  const double* inv_din;
+  const int32_t* din;
+  const int32_t* int_of;
+  int32_t n;
+  int32_t B;
+  int32_t W;
+  int32_t nlong_fwd;
+  int32_t nlong_back;
+  int32_t pad;
+  double R;           // total sample parameter of the block's graph
+  int64_t base;       // first flat element of the block
+  int64_t node_base;  // first flat node of the block (arrays of length n)
+  int64_t long_base;  // first long-row slot (x B) of the block
+  int64_t src_base;   // first source / output index of the block
+};
+
+struct MTile {
+  int32_t entry;
+  int32_t row0;
+  int32_t row1;  // < 0: chunk of long row slot (-row1 - 1)
+  int32_t e0;
+  int32_t e1;
+  int32_t row;   // long chunk: the row
+};
+
+struct LongRow {
+  int32_t entry;
+  int32_t row;
+  int32_t slot;
+  int32_t pad;
+};
+
+// ---- level operators ------------------------------------------------------
+
+struct FwdOp {
+  using V = int64_t;
+  static constexpr bool kForward = true;
+  const int64_t* __restrict__ qprev;
+  int64_t* __restrict__ qnext;
+  double* __restrict__ lvl;
+  long long* __restrict__ acc;  // long rows
+  double sc;
+  __device__ __forceinline__ V gather(const BEntry& E, int32_t col, int sub) const {
+    return qprev[E.base + (int64_t)col * E.B + sub];
+  }
+  __device__ __forceinline__ void epi(const BEntry& E, int32_t r, int sub, V a) const {
+    const int64_t i = E.base + (int64_t)r * E.B + sub;
+    const double p = sc * ((double)a * kFixInv);
+    lvl[i] = p;
+    qnext[i] = (int64_t)rint((p * E.inv_din[r]) * kFix);
+  }
+  __device__ __forceinline__ void long_add(const BEntry& E, int32_t slot, int sub, V a) const {
+    atomicAdd((unsigned long long*)&acc[(E.long_base + slot) * kBatchMaxB + sub], (unsigned long long)a);
+  }
+  __device__ __forceinline__ V long_take(const BEntry& E, int32_t slot, int sub) const {
+    long long* p = &acc[(E.long_base + slot) * kBatchMaxB + sub];
+    const long long v = *p;
+    *p = 0;
+    return v;
+  }
+};
+
+struct BackOp {
+  using V = double;
+  static constexpr bool kForward = false;
+  const double* __restrict__ sprev;
+  double* __restrict__ snext;
+  const double* __restrict__ D;
+  const double* __restrict__ lvl;  // level L - l
+  double* __restrict__ acc;
+  double sc, a;
+  __device__ __forceinline__ V gather(const BEntry& E, int32_t col, int sub) const {
+    return sprev[E.base + (int64_t)col * E.B + sub];
+  }
+  __device__ __forceinline__ void epi(const BEntry& E, int32_t r, int sub, V v) const {
+    const int64_t i = E.base + (int64_t)r * E.B + sub;
+    snext[i] = sc * (E.inv_din[r] * v) + a * (D[i] * lvl[i]);
+  }
+  __device__ __forceinline__ void long_add(const BEntry& E, int32_t slot, int sub, V v) const {
+    atomicAdd(&acc[(E.long_base + slot) * kBatchMaxB + sub], v);
+  }
+  __device__ __forceinline__ V long_take(const BEntry& E, int32_t slot, int sub) const {
+    double* p = &acc[(E.long_base + slot) * kBatchMaxB + sub];
+    const double v = *p;
+    *p = 0.0;
+    return v;
+  }
+};
+
+template <class Op>
+__global__ __launch_bounds__(kSpmmThreads) void spmm_kernel(const MTile* __restrict__ tiles, int32_t ntiles,
+                                                            const BEntry* __restrict__ ents, Op op) {
+  using V = typename Op::V;
+  const int wave = blockIdx.x * (kSpmmThreads / 64) + (threadIdx.x >> 6);
+  if (wave >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const MTile t = tiles[wave];
+  const BEntry E = ents[t.entry];
+  const int W = E.W;
+  const int P = 64 / W;
+  const int grp = lane / W, sub = lane - grp * W;
+  const bool vb = sub < E.B;
+  const int32_t* __restrict__ off = Op::kForward ? E.out_off : E.in_off;
+  const int32_t* __restrict__ idx = Op::kForward ? E.out_idx : E.in_idx;
+  if (t.row1 >= 0) {
+    for (int32_t r = t.row0 + grp; r < t.row1; r += P) {
+      const int32_t e0 = off[r], e1 = off[r + 1];
+      V acc = 0;
+      int32_t e = e0;
+      for (; e + 4 <= e1; e += 4) {
+        const int32_t c0 = idx[e], c1 = idx[e + 1], c2 = idx[e + 2], c3 = idx[e + 3];
+        if (vb) {
+          const V v0 = op.gather(E, c0, sub), v1 = op.gather(E, c1, sub);
+          const V v2 = op.gather(E, c2, sub), v3 = op.gather(E, c3, sub);
+          acc += v0;
+          acc += v1;
+          acc += v2;
+          acc += v3;
+        }
+      }
+      for (; e < e1; ++e) {
+        const int32_t c0 = idx[e];
+        if (vb) acc += op.gather(E, c0, sub);
+      }
+      if (vb) op.epi(E, r, sub, acc);
+    }
+  } else {
+    V acc = 0;
+    for (int32_t e = t.e0 + grp; e < t.e1; e += P) {
+      const int32_t c0 = idx[e];
+      if (vb) acc += op.gather(E, c0, sub);
+    }
+    for (int m = W; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+    if (grp == 0 && vb) op.long_add(E, -t.row1 - 1, sub, acc);
+  }
+}
+
+template <class Op>
+__global__ void long_finish_kernel(const LongRow* __restrict__ rows, int32_t nrows, const BEntry* __restrict__ ents,
+                                   Op op) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t lr = i / kBatchMaxB;
+  const int sub = (int)(i % kBatchMaxB);
+  if (lr >= nrows) return;
+  const LongRow L = rows[lr];
+  const BEntry E = ents[L.entry];
+  if (sub >= E.B) return;
+  op.epi(E, L.row, sub, op.long_take(E, L.slot, sub));
+}
+
+// ---- per-block elementwise kernels (grid.y = block) -------------------------
+
+__global__ void bat_forward_init(const BEntry* __restrict__ ents, const int32_t* __restrict__ src_int, double pi0,
+                                 double* __restrict__ lvl0, int64_t* __restrict__ q0) {
+  const BEntry E = ents[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (int64_t)E.n * E.B;
+  if (i >= nb) return;
+  const int32_t r = (int32_t)(i / E.B);
+  const int32_t b = (int32_t)(i - (int64_t)r * E.B);
+  const bool hit = src_int[E.src_base + b] == r;
+  lvl0[E.base + i] = hit ? pi0 : 0.0;
+  q0[E.base + i] = hit ? (int64_t)rint((pi0 * E.inv_din[r]) * kFix) : 0;
+}
+
+__global__ void bat_sum_levels(int64_t NB, int32_t L, const double* __restrict__ levels, double* __restrict__ pi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NB) return;
+  double acc = levels[i];
+  for (int l = 1; l <= L; ++l) acc = acc + levels[(int64_t)l * NB + i];
+  pi[i] = acc;
+}
+
+__global__ void bat_budget(const BEntry* __restrict__ ents, const double* __restrict__ pi, int32_t alloc,
+                           int32_t exact_small_din, uint64_t* __restrict__ Rk) {
+  const BEntry E = ents[blockIdx.y];
+  const double R = E.R;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (int64_t)E.n * E.B;
+  if (i >= nb) return;
+  const int32_t r = (int32_t)(i / E.B);
+  const double p = pi[E.base + i];
+  const double want = alloc == ES_ALLOC_PI ? R * p : R * (p * p);
+  uint64_t c = (uint64_t)ceil(want);
+  if (p == 0.0) c = 0;
+  if (exact_small_din && E.din[r] <= 1) c = 0;
+  Rk[E.base + i] = c;
+}
+
+// One wave per node: sort the block's B counts ascending into T, Rmax = largest.
+__global__ void bat_sort_counts(const BEntry* __restrict__ ents, const uint64_t* __restrict__ Rk,
+                                uint64_t* __restrict__ T, uint64_t* __restrict__ Rmax) {
+  const BEntry E = ents[blockIdx.y];
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= E.n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = E.base + r * E.B;
+  // lanes past B hold 0 and sort first; the B real counts end up in lanes 64-B..63
+  uint64_t v = lane < E.B ? Rk[row + lane] : 0ull;
+  for (int size = 2; size <= 64; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t o = __shfl_xor(v, stride, 64);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      // ascending runs where up, descending otherwise
+      const bool take_min = (lower == up);
+      v = take_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  const int j = lane - (64 - E.B);
+  if (j >= 0) T[row + j] = v;
+  if (lane == 63) Rmax[E.node_base + r] = v;
+}
+
+// M_b(k) = sum_{j <= #{b' : R_b'(k) < R_b(k)}} H[k][j];  D^ as in the single-source path.
+__global__ void bat_finish_diag(const BEntry* __restrict__ ents, const uint64_t* __restrict__ Rk,
+                                const uint64_t* __restrict__ T, const uint64_t* __restrict__ H, double c,
+                                int32_t exact_small_din, double* __restrict__ D, unsigned long long* __restrict__ sums) {
+  const BEntry E = ents[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (int64_t)E.n * E.B;
+  unsigned long long req = 0, met = 0;
+  if (i < nb) {
+    const int32_t r = (int32_t)(i / E.B);
+    const int64_t row = E.base + (int64_t)r * E.B;
+    const uint64_t R = Rk[E.base + i];
+    double d = 1.0;
+    if (R > 0) {
+      int32_t lo = 0, hi = E.B;  // first threshold >= R
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (T[row + mid] < R) lo = mid + 1;
+        else hi = mid;
+      }
+      uint64_t M = 0;
+      for (int32_t j = 0; j <= lo && j < E.B; ++j) M += H[row + j];
+      d = (double)(R - M) / (double)R;
+      req = R;
+      met = M;
+    }
+    if (exact_small_din) {
+      const int32_t din = E.din[r];
+      if (din == 0) d = 1.0;
+      else if (din == 1) d = 1.0 - c;
+    }
+    D[E.base + i] = d;
+  }
+  for (int m = 32; m > 0; m >>= 1) {
+    req += __shfl_xor(req, m, 64);
+    met += __shfl_xor(met, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (req | met)) {
+    atomicAdd(&sums[0], req);
+    atomicAdd(&sums[1], met);
+  }
+}
+
+__global__ void bat_back_init(int64_t NB, double a, const double* __restrict__ D, const double* __restrict__ lvlL,
+                              double* __restrict__ s0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NB) return;
+  s0[i] = a * (D[i] * lvlL[i]);
+}
+
+// s_out[q][v] = S[int_of[v]][b] for external node v
+__global__ void bat_output(const BEntry* __restrict__ ents, const double* __restrict__ S, double* const* __restrict__ outs) {
+  const BEntry E = ents[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (int64_t)E.n * E.B;
+  if (i >= nb) return;
+  const int32_t b = (int32_t)(i / E.n);
+  const int32_t v = (int32_t)(i - (int64_t)b * E.n);
+  outs[E.src_base + b][v] = S[E.base + (int64_t)E.int_of[v] * E.B + b];
+}
+
+__global__ void bat_accumulate_walk(const WalkTotals* __restrict__ tot, unsigned long long* __restrict__ sums) {
+  sums[2] += tot->total;
+  sums[3] += tot->meets;
+}
+
+__global__ void zero_u64(int64_t n, unsigned long long* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace
+
+// ---- plans -------------------------------------------------------------------
+
+struct BatchBlock {
+  const es_graph* g;
+  int32_t B;
+  int32_t W, G;
+  std::vector<int32_t> queries;  // query indices
+};
+
+struct BatchPlan {
+  BatchPlan* next = nullptr;
+  // key
+  std::vector<const es_graph*> kg;
+  std::vector<int32_t> kB, kW, kG;
+  int32_t L = 0;
+  double c = 0, eps = 0, r_scale = 0;
+  uint64_t seed = 0;
+  int32_t alloc = 0, small = 0;
+  int32_t nq = 0;
+  // device data
+  BEntry* ents = nullptr;
+  int32_t nent = 0;
+  MTile* tiles_fwd = nullptr;
+  MTile* tiles_back = nullptr;
+  int32_t ntf = 0, ntb = 0;
+  LongRow* long_fwd = nullptr;
+  LongRow* long_back = nullptr;
+  int32_t nlf = 0, nlb = 0;
+  int32_t* src_int = nullptr;    // [nq] internal source ids, block order
+  double** outs = nullptr;       // [nq] device pointer array, block order
+  int64_t NB = 0, NN = 0, NLONG = 0;
+  int32_t max_nb_blocks = 0;     // grid.x for per-block elementwise kernels
+  int32_t max_n = 0;
+  std::vector<int64_t> node_base, base;
+  std::vector<int32_t> order;    // block-order position -> query index
+  // workspace pointers the plan was built with (a change forces a rebuild)
+  std::vector<void*> ws;
+  hipGraphExec_t exec = nullptr;
+};
+
+void free_batch_plans(es_ctx* ctx) {
+  BatchPlan* p = ctx->plans;
+  while (p) {
+    BatchPlan* nx = p->next;
+    hipFree(p->ents);
+    hipFree(p->tiles_fwd);
+    hipFree(p->tiles_back);
+    hipFree(p->long_fwd);
+    hipFree(p->long_back);
+    hipFree(p->src_int);
+    hipFree(p->outs);
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    delete p;
+    p = nx;
+  }
+  ctx->plans = nullptr;
+}
+
+namespace {
+
+// Tiles over the rows of one block for one CSR direction.
+void make_tiles(const std::vector<int32_t>& off, int32_t n, int32_t entry, int32_t W, int32_t G,
+                std::vector<MTile>& tiles, std::vector<LongRow>& longs, int32_t& nlong) {
+  const int32_t P = 64 / W;
+  const int64_t target = (int64_t)P * G;
+  int32_t r = 0;
+  while (r < n) {
+    const int32_t deg = off[r + 1] - off[r];
+    if (deg > kLongRow) {
+      const int32_t slot = nlong++;
+      for (int32_t e0 = off[r]; e0 < off[r + 1]; e0 += kLongRow)
+        tiles.push_back(MTile{entry, r, -(slot + 1), e0, std::min(e0 + kLongRow, off[r + 1]), r});
+      longs.push_back(LongRow{entry, r, slot, 0});
+      ++r;
+      continue;
+    }
+    const int32_t r0 = r;
+    int64_t acc = 0;
+    while (r < n) {
+      const int32_t d = off[r + 1] - off[r];
+      if (d > kLongRow) break;
+      const int64_t w = std::max<int32_t>(d, 1);
+      if (r > r0 && acc + w > target) break;
+      acc += w;
+      ++r;
+    }
+    tiles.push_back(MTile{entry, r0, r, 0, 0, 0});
+  }
+}
+
+int32_t pow2_at_least(int32_t x) {
+  int32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+bool find_tuned(const es_graph* g, int32_t B, int32_t* W, int32_t* G) {
+  for (auto& t : g->tuned)
+    if (t.first == B) {
+      *W = t.second.first;
+      *G = t.second.second;
+      return true;
+    }
+  return false;
+}
+
+template <class T>
+es_status upload(es_ctx* ctx, T** dptr, const std::vector<T>& h) {
+  ES_CHECK_HIP(ctx, hipMalloc((void**)dptr, sizeof(T) * std::max<size_t>(1, h.size())));
+  if (!h.empty()) ES_CHECK_HIP(ctx, hipMemcpy(*dptr, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return ES_OK;
+}
+
+struct BatchBuffers {
+  double* levels;
+  int64_t* q[2];
+  double* pi;
+  uint64_t* Rk;
+  uint64_t* T;
+  uint64_t* H;
+  double* D;
+  double* s[2];
+  uint64_t* Rmax;
+  long long* acc;
+  unsigned long long* sums;  // [0] pairs requested, [1] meets, [2] pairs simulated, [3] raw meets
+};
+
+es_status batch_buffers(es_ctx* ctx, const BatchPlan& p, BatchBuffers* b) {
+  es_status st;
+  const size_t NB = (size_t)p.NB;
+  const size_t L1 = (size_t)p.L + 1;
+  b->levels = (double*)workspace(ctx, kWsLevels, 8 * NB * L1, &st);
+  if (!b->levels) return st;
+  b->q[0] = (int64_t*)workspace(ctx, kWsQ0, 8 * NB, &st);
+  if (!b->q[0]) return st;
+  b->q[1] = (int64_t*)workspace(ctx, kWsQ1, 8 * NB, &st);
+  if (!b->q[1]) return st;
+  b->pi = (double*)workspace(ctx, kWsPi, 8 * NB, &st);
+  if (!b->pi) return st;
+  b->Rk = (uint64_t*)workspace(ctx, kWsRk, 8 * NB, &st);
+  if (!b->Rk) return st;
+  b->H = (uint64_t*)workspace(ctx, kWsM, 8 * NB, &st);
+  if (!b->H) return st;
+  b->D = (double*)workspace(ctx, kWsD, 8 * NB, &st);
+  if (!b->D) return st;
+  b->s[0] = (double*)workspace(ctx, kWsS0, 8 * NB, &st);
+  if (!b->s[0]) return st;
+  b->s[1] = (double*)workspace(ctx, kWsS1, 8 * NB, &st);
+  if (!b->s[1]) return st;
+  b->T = (uint64_t*)workspace(ctx, kWsBatchT, 8 * NB, &st);
+  if (!b->T) return st;
+  char* misc = (char*)workspace(ctx, kWsBatchMisc,
+                                8 * (size_t)p.NN + 8 * (size_t)std::max<int64_t>(1, p.NLONG) * kBatchMaxB + 64, &st);
+  if (!misc) return st;
+  b->Rmax = (uint64_t*)misc;
+  b->acc = (long long*)(misc + 8 * (size_t)p.NN);
+  b->sums = (unsigned long long*)(misc + 8 * (size_t)p.NN + 8 * (size_t)std::max<int64_t>(1, p.NLONG) * kBatchMaxB);
+  return ES_OK;
+}
+
+// Enqueue the whole batch on ctx->stream (also used under stream capture).
+es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
+                        const std::vector<const es_graph*>& block_graphs, uint64_t seed) {
+  hipStream_t stream = ctx->stream;
+  const double sc = std::sqrt(p.c);
+  const double a = 1.0 / (1.0 - sc);
+  const int tb = 256;
+  const int64_t NB = p.NB;
+  const int64_t nacc = std::max<int64_t>(1, p.NLONG) * kBatchMaxB;
+  dim3 egrid(p.max_nb_blocks, p.nent);
+  zero_u64<<<1, 64, 0, stream>>>(4, b.sums);
+  zero_u64<<<ceil_div(nacc, tb), tb, 0, stream>>>(nacc, (unsigned long long*)b.acc);
+  bat_forward_init<<<egrid, tb, 0, stream>>>(p.ents, p.src_int, 1.0 - sc, b.levels, b.q[0]);
+  const int spmm_f = ceil_div(p.ntf, kSpmmThreads / 64);
+  const int spmm_b = ceil_div(p.ntb, kSpmmThreads / 64);
+  for (int32_t l = 1; l <= p.L; ++l) {
+    FwdOp op{b.q[(l - 1) & 1], b.q[l & 1], b.levels + (int64_t)l * NB, b.acc, sc};
+    if (p.ntf) spmm_kernel<FwdOp><<<spmm_f, kSpmmThreads, 0, stream>>>(p.tiles_fwd, p.ntf, p.ents, op);
+    if (p.nlf)
+      long_finish_kernel<FwdOp><<<ceil_div((int64_t)p.nlf * kBatchMaxB, tb), tb, 0, stream>>>(p.long_fwd, p.nlf,
+                                                                                               p.ents, op);
+  }
+  bat_sum_levels<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, p.L, b.levels, b.pi);
+  bat_budget<<<egrid, tb, 0, stream>>>(p.ents, b.pi, p.alloc, p.small, b.Rk);
+  dim3 sgrid(ceil_div(p.max_n, tb / 64), p.nent);
+  bat_sort_counts<<<sgrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.Rmax);
+  for (int32_t e = 0; e < p.nent; ++e) {
+    const es_graph* g = block_graphs[e];
+    const int32_t B = p.kB[e];
+    WalkTotals* tot = nullptr;
+    ES_TRY(launch_walks_buckets(ctx, g, b.Rmax + p.node_base[e], b.T + p.base[e], B, seed, p.c, b.H + p.base[e],
+                                &tot));
+    bat_accumulate_walk<<<1, 1, 0, stream>>>(tot, b.sums);
+  }
+  bat_finish_diag<<<egrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.H, p.c, p.small, b.D, b.sums);
+  // back-accumulation; level L lands in s[L & 1]
+  bat_back_init<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, a, b.D, b.levels + (int64_t)p.L * NB, b.s[0]);
+  for (int32_t l = 1; l <= p.L; ++l) {
+    BackOp op{b.s[(l - 1) & 1], b.s[l & 1], b.D, b.levels + (int64_t)(p.L - l) * NB, (double*)b.acc, sc, a};
+    if (p.ntb) spmm_kernel<BackOp><<<spmm_b, kSpmmThreads, 0, stream>>>(p.tiles_back, p.ntb, p.ents, op);
+    if (p.nlb)
+      long_finish_kernel<BackOp><<<ceil_div((int64_t)p.nlb * kBatchMaxB, tb), tb, 0, stream>>>(p.long_back, p.nlb,
+                                                                                                p.ents, op);
+  }
+  bat_output<<<egrid, tb, 0, stream>>>(p.ents, b.s[p.L & 1], p.outs);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+bool same_key(const BatchPlan& p, const BatchPlan& q) {
+  return p.kg == q.kg && p.kB == q.kB && p.kW == q.kW && p.kG == q.kG && p.L == q.L && p.c == q.c &&
+         p.eps == q.eps && p.r_scale == q.r_scale && p.seed == q.seed && p.alloc == q.alloc && p.small == q.small &&
+         p.nq == q.nq;
+}
+
+// Build tiles and descriptors of a plan whose key fields are set.
+es_status build_batch_plan(es_ctx* ctx, BatchPlan& p, const std::vector<BatchBlock>& blocks) {
+  std::vector<BEntry> ents;
+  std::vector<MTile> tf, tbk;
+  std::vector<LongRow> lf, lbk;
+  int64_t base = 0, node_base = 0, long_base = 0, src_base = 0;
+  p.max_n = 1;
+  int64_t max_nb = 1;
+  p.node_base.clear();
+  p.base.clear();
+  for (size_t e = 0; e < blocks.size(); ++e) {
+    const BatchBlock& bl = blocks[e];
+    const es_graph* g = bl.g;
+    BEntry E{};
+    E.out_off = g->out_off;
+    E.out_idx = g->out_idx;
+    E.in_off = g->in_off;
+    E.in_idx = g->in_idx;
+    E.inv_din = g->inv_din;
+    E.din = g->din_int;
+    E.int_of = g->int_of;
+    E.n = g->n;
+    E.B = bl.B;
+    E.W = bl.W;
+    E.R = total_samples(g->n, p.c, p.eps, p.r_scale);
+    E.base = base;
+    E.node_base = node_base;
+    E.long_base = long_base;
+    E.src_base = src_base;
+    int32_t nlf = 0, nlb = 0;
+    make_tiles(g->h_out_off, g->n, (int32_t)e, bl.W, bl.G, tf, lf, nlf);
+    const size_t lf_before = lbk.size();
+    (void)lf_before;
+    // backward chunks use slots after the forward ones of the same block
+    std::vector<MTile> tb_e;
+    std::vector<LongRow> lb_e;
+    make_tiles(g->h_in_off, g->n, (int32_t)e, bl.W, bl.G, tb_e, lb_e, nlb);
+    for (auto& t : tb_e) {
+      if (t.row1 < 0) t.row1 = -((-t.row1 - 1) + nlf + 1);
+      tbk.push_back(t);
+    }
+    for (auto& r : lb_e) {
+      r.slot += nlf;
+      lbk.push_back(r);
+    }
+    E.nlong_fwd = nlf;
+    E.nlong_back = nlb;
+    ents.push_back(E);
+    p.base.push_back(base);
+    p.node_base.push_back(node_base);
+    base += (int64_t)g->n * bl.B;
+    node_base += g->n;
+    long_base += nlf + nlb;
+    src_base += bl.B;
+    p.max_n = std::max(p.max_n, g->n);
+    max_nb = std::max<int64_t>(max_nb, (int64_t)g->n * bl.B);
+  }
+  p.NB = base;
+  p.NN = node_base;
+  p.NLONG = long_base;
+  p.nent = (int32_t)ents.size();
+  p.ntf = (int32_t)tf.size();
+  p.ntb = (int32_t)tbk.size();
+  p.nlf = (int32_t)lf.size();
+  p.nlb = (int32_t)lbk.size();
+  p.max_nb_blocks = ceil_div(max_nb, 256);
+  ES_TRY(upload(ctx, &p.ents, ents));
+  ES_TRY(upload(ctx, &p.tiles_fwd, tf));
+  ES_TRY(upload(ctx, &p.tiles_back, tbk));
+  ES_TRY(upload(ctx, &p.long_fwd, lf));
+  ES_TRY(upload(ctx, &p.long_back, lbk));
+  ES_CHECK_HIP(ctx, hipMalloc((void**)&p.src_int, sizeof(int32_t) * std::max(1, p.nq)));
+  ES_CHECK_HIP(ctx, hipMalloc((void**)&p.outs, sizeof(double*) * std::max(1, p.nq)));
+  return ES_OK;
+}
+
+// Time the forward SpMM of one block for each candidate tiling; keep the fastest.
+es_status autotune(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opts* o, int32_t* bestW,
+                   int32_t* bestG) {
+  std::vector<int32_t> widths;
+  for (int32_t w = pow2_at_least(std::max(B, 1)); w <= 64; w <<= 1) widths.push_back(std::max(w, 8));
+  widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+  const int32_t rows_opts[] = {8, 32, 128};
+  float best = 1e30f;
+  *bestW = widths.front();
+  *bestG = 32;
+  hipEvent_t e0 = ctx->ev[6], e1 = ctx->ev[7];
+  for (int32_t W : widths) {
+    for (int32_t G : rows_opts) {
+      BatchPlan p;
+      p.c = o->c;
+      p.eps = o->eps;
+      p.r_scale = o->r_scale;
+      p.L = 3;
+      p.nq = B;
+      std::vector<BatchBlock> blocks(1);
+      blocks[0].g = g;
+      blocks[0].B = B;
+      blocks[0].W = W;
+      blocks[0].G = G;
+      es_status st = build_batch_plan(ctx, p, blocks);
+      BatchBuffers bb{};
+      if (st == ES_OK) st = batch_buffers(ctx, p, &bb);
+      if (st == ES_OK) {
+        // sources: the B highest-degree nodes (internal ids 0..B-1)
+        std::vector<int32_t> src(B);
+        for (int32_t b = 0; b < B; ++b) src[b] = std::min(b, g->n - 1);
+        hipMemcpy(p.src_int, src.data(), 4 * B, hipMemcpyHostToDevice);
+        const double sc = std::sqrt(o->c);
+        dim3 egrid(p.max_nb_blocks, 1);
+        bat_forward_init<<<egrid, 256, 0, ctx->stream>>>(p.ents, p.src_int, 1.0 - sc, bb.levels, bb.q[0]);
+        const int spmm_f = ceil_div(p.ntf, kSpmmThreads / 64);
+        float tot = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+          hipEventRecord(e0, ctx->stream);
+          for (int32_t l = 1; l <= p.L; ++l) {
+            FwdOp op{bb.q[(l - 1) & 1], bb.q[l & 1], bb.levels + (int64_t)l * p.NB, bb.acc, sc};
+            if (p.ntf) spmm_kernel<FwdOp><<<spmm_f, kSpmmThreads, 0, ctx->stream>>>(p.tiles_fwd, p.ntf, p.ents, op);
+            if (p.nlf)
+              long_finish_kernel<FwdOp><<<ceil_div((int64_t)p.nlf * kBatchMaxB, 256), 256, 0, ctx->stream>>>(
+                  p.long_fwd, p.nlf, p.ents, op);
+          }
+          hipEventRecord(e1, ctx->stream);
+          hipEventSynchronize(e1);
+          float ms = 0;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (rep == 1) tot = ms;
+        }
+        if (tot < best) {
+          best = tot;
+          *bestW = W;
+          *bestG = G;
+        }
+      }
+      hipFree(p.ents);
+      hipFree(p.tiles_fwd);
+      hipFree(p.tiles_back);
+      hipFree(p.long_fwd);
+      hipFree(p.long_back);
+      hipFree(p.src_int);
+      hipFree(p.outs);
+      ES_TRY(st);
+    }
+  }
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+}  // namespace
+}  // namespace es
+
+using namespace es;
+
+extern "C" {
+
+es_status es_batch_tuning(const es_graph* g, int32_t B, int32_t* width, int32_t* rows) {
+  if (!g || !width || !rows) return ES_EINVAL;
+  if (!find_tuned(g, B, width, rows)) {
+    *width = 0;
+    *rows = 0;
+  }
+  return ES_OK;
+}
+
+es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, const int32_t* graph_of_query,
+                   const int32_t* sources, int32_t nq, const es_query_opts* o, const es_batch_opts* bo,
+                   double* const* s_out, es_stats* stats) {
+  if (!ctx || !graphs || ngraphs < 1 || !graph_of_query || !sources || nq < 1 || !o || !s_out) return ES_EINVAL;
+  if (!(o->c > 0.0 && o->c <= 0.99)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", o->c);
+  if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ctx, ES_EINVAL, "eps=%g outside (0, 1)", o->eps);
+  if (!(o->r_scale > 0.0)) return fail(ctx, ES_EINVAL, "r_scale=%g must be positive", o->r_scale);
+  if (o->d_override) return fail(ctx, ES_EUNSUPPORTED, "d_override is single-source only");
+  if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI)
+    return fail(ctx, o->alloc == ES_ALLOC_LEARNED ? ES_EUNSUPPORTED : ES_EINVAL, "allocation %d", o->alloc);
+  es_batch_opts defaults{0, 1, 0, 0};
+  const es_batch_opts& b = bo ? *bo : defaults;
+  if (b.force_width && (b.force_width < 8 || b.force_width > 64 || (b.force_width & (b.force_width - 1))))
+    return fail(ctx, ES_EINVAL, "force_width=%d", b.force_width);
+  if (b.force_rows < 0) return fail(ctx, ES_EINVAL, "force_rows=%d", b.force_rows);
+  for (int32_t gi = 0; gi < ngraphs; ++gi)
+    if (!graphs[gi]) return fail(ctx, ES_EINVAL, "graph %d is NULL", gi);
+  for (int32_t q = 0; q < nq; ++q) {
+    const int32_t gi = graph_of_query[q];
+    if (gi < 0 || gi >= ngraphs) return fail(ctx, ES_EINVAL, "query %d: graph index %d", q, gi);
+    if (sources[q] < 0 || sources[q] >= graphs[gi]->n) return fail(ctx, ES_EINVAL, "query %d: source %d", q, sources[q]);
+    if (!s_out[q]) return fail(ctx, ES_EINVAL, "query %d: null output", q);
+  }
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  for (int32_t gi = 0; gi < ngraphs; ++gi) {
+    const double R = total_samples(graphs[gi]->n, o->c, o->eps, o->r_scale);
+    if (R + (double)graphs[gi]->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
+  }
+  // blocks of at most 64 queries per graph, in graph order
+  std::vector<BatchBlock> blocks;
+  for (int32_t gi = 0; gi < ngraphs; ++gi) {
+    std::vector<int32_t> qs;
+    for (int32_t q = 0; q < nq; ++q)
+      if (graph_of_query[q] == gi) qs.push_back(q);
+    for (size_t s0 = 0; s0 < qs.size(); s0 += kBatchMaxB) {
+      BatchBlock bl;
+      bl.g = graphs[gi];
+      bl.queries.assign(qs.begin() + s0, qs.begin() + std::min(qs.size(), s0 + kBatchMaxB));
+      bl.B = (int32_t)bl.queries.size();
+      blocks.push_back(bl);
+    }
+  }
+  // tiling per block: forced, tuned or default
+  for (auto& bl : blocks) {
+    int32_t W = 0, G = 0;
+    if (b.force_width || b.force_rows) {
+      W = b.force_width ? b.force_width : std::max(8, pow2_at_least(bl.B));
+      G = b.force_rows ? b.force_rows : 32;
+      if (W < bl.B) return fail(ctx, ES_EINVAL, "force_width=%d below block width %d", W, bl.B);
+    } else if (!find_tuned(bl.g, bl.B, &W, &G)) {
+      if (b.autotune) {
+        ES_TRY(autotune(ctx, bl.g, bl.B, o, &W, &G));
+        const_cast<es_graph*>(bl.g)->tuned.push_back({bl.B, {W, G}});
+      } else {
+        W = std::max(8, pow2_at_least(bl.B));
+        G = 32;
+      }
+    }
+    bl.W = W;
+    bl.G = G;
+  }
+  // plan lookup
+  BatchPlan key;
+  for (auto& bl : blocks) {
+    key.kg.push_back(bl.g);
+    key.kB.push_back(bl.B);
+    key.kW.push_back(bl.W);
+    key.kG.push_back(bl.G);
+  }
+  key.L = num_levels(o->c, o->eps);
+  key.c = o->c;
+  key.eps = o->eps;
+  key.r_scale = o->r_scale;
+  key.seed = o->seed;
+  key.alloc = o->alloc;
+  key.small = o->exact_small_din;
+  key.nq = nq;
+  BatchPlan* plan = nullptr;
+  for (BatchPlan* p = ctx->plans; p; p = p->next)
+    if (same_key(*p, key)) plan = p;
+  if (!plan) {
+    plan = new BatchPlan(key);
+    plan->next = nullptr;
+    const es_status st = build_batch_plan(ctx, *plan, blocks);
+    if (st != ES_OK) {
+      BatchPlan* saved = ctx->plans;
+      ctx->plans = plan;  // free_batch_plans releases exactly this one
+      free_batch_plans(ctx);
+      ctx->plans = saved;
+      return st;
+    }
+    // keep at most eight plans: drop the oldest
+    int count = 0;
+    for (BatchPlan* q = ctx->plans; q; q = q->next)
+      if (++count >= 8 && q->next) {
+        hipStreamSynchronize(ctx->stream);  // an evicted graph may still be running
+        BatchPlan* rest = q->next;
+        q->next = nullptr;
+        BatchPlan* saved = ctx->plans;
+        ctx->plans = rest;
+        free_batch_plans(ctx);
+        ctx->plans = saved;
+        break;
+      }
+    plan->next = ctx->plans;
+    ctx->plans = plan;
+  }
+  // workspaces (allocated before any capture)
+  BatchBuffers bb{};
+  ES_TRY(batch_buffers(ctx, *plan, &bb));
+  ES_TRY(lifetime_table(ctx, o->c));
+  {
+    es_status st;
+    const int nbk = ceil_div(plan->max_n, 1024);
+    if (!workspace(ctx, kWsTotals, sizeof(WalkTotals), &st)) return st;
+    if (!workspace(ctx, kWsScanCnt, sizeof(uint32_t) * nbk, &st)) return st;
+    if (!workspace(ctx, kWsScanSum, sizeof(uint64_t) * nbk, &st)) return st;
+    if (!workspace(ctx, kWsActive, sizeof(int32_t) * (size_t)plan->max_n, &st)) return st;
+    if (!workspace(ctx, kWsPrefix, sizeof(uint64_t) * ((size_t)plan->max_n + 1), &st)) return st;
+  }
+  std::vector<void*> ws_now(ctx->ws.begin(), ctx->ws.end());
+  if (plan->exec && plan->ws != ws_now) {
+    hipGraphExecDestroy(plan->exec);
+    plan->exec = nullptr;
+  }
+  // per-call inputs: sources (internal ids) and output pointers, in block order
+  std::vector<int32_t> src_int;
+  std::vector<double*> outs;
+  std::vector<const es_graph*> block_graphs;
+  for (auto& bl : blocks) {
+    block_graphs.push_back(bl.g);
+    for (int32_t q : bl.queries) {
+      src_int.push_back(bl.g->h_int_of[sources[q]]);
+      outs.push_back(s_out[q]);
+    }
+  }
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(plan->src_int, src_int.data(), 4 * src_int.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(plan->outs, outs.data(), sizeof(double*) * outs.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+  ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+  if (b.use_hip_graph) {
+    if (!plan->exec) {
+      if (!ctx->capture_stream) ES_CHECK_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      // the inputs above must land before the captured work reads them
+      ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      hipStream_t user = ctx->stream;
+      ctx->stream = ctx->capture_stream;
+      ES_CHECK_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      es_status st = enqueue_batch(ctx, *plan, bb, block_graphs, o->seed);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+      ctx->stream = user;
+      ES_TRY(st);
+      if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamEndCapture");
+      const hipError_t ei = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ei != hipSuccess) return hip_fail(ctx, ei, "hipGraphInstantiate");
+      plan->ws = ws_now;
+    }
+    ES_CHECK_HIP(ctx, hipGraphLaunch(plan->exec, ctx->stream));
+  } else {
+    ES_TRY(enqueue_batch(ctx, *plan, bb, block_graphs, o->seed));
+  }
+  ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+  if (stats) {
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long h[4];
+    ES_CHECK_HIP(ctx, hipMemcpy(h, bb.sums, sizeof(h), hipMemcpyDeviceToHost));
+    es_stats s{};
+    s.L = plan->L;
+    s.R = plan->nent ? total_samples(blocks[0].g->n, o->c, o->eps, o->r_scale) : 0.0;
+    s.pairs_requested = h[0];
+    s.meets = h[1];
+    s.pairs = h[2];
+    float ms = 0;
+    ES_CHECK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    s.ms_walk = ms;
+    *stats = s;
+  }
+  return ES_OK;
+}
+
+}  // extern "C"

@@ -272,6 +272,8 @@ es_status es_ctx_destroy(es_ctx* ctx) {
   if (!ctx) return ES_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  es::free_batch_plans(ctx);
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   for (void* p : ctx->ws) hipFree(p);
   hipFree(ctx->thr);
   hipFree(ctx->mlp_w);
@@ -358,6 +360,8 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
     return hip_fail(ctx, e, "graph upload");
   }
   g->h_int_of = std::move(h.int_of);
+  g->h_out_off = h.out_off;
+  g->h_in_off = h.in_off;
   es_status st = build_plan(ctx, h.out_off.data(), n, &g->fwd);
   if (st == ES_OK) st = build_plan(ctx, h.in_off.data(), n, &g->back);
   if (st != ES_OK) {

@@ -46,6 +46,8 @@ struct SpmvPlan {
   int32_t max_row_nnz = 0;
 };
 
+struct BatchPlan;
+
 }  // namespace es
 
 // Device graph.  Nodes are stored under internal ids: the rank of the node by
@@ -66,6 +68,9 @@ struct es_graph {
   int32_t* ext_of = nullptr;   // [n]    internal id -> external id
   int32_t* int_of = nullptr;   // [n]    external id -> internal id
   std::vector<int32_t> h_int_of;
+  std::vector<int32_t> h_out_off, h_in_off;  // host copies of the offsets (batch tiling)
+  // autotuned batch tiling per source-block width B: (lanes per row, entries per lane)
+  std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> tuned;
   es::SpmvPlan fwd;            // over the out-CSR
   es::SpmvPlan back;           // over the in-CSR
 };
@@ -86,6 +91,9 @@ struct es_ctx {
   hipEvent_t ev_walk_begin = nullptr;  // set while a query records stage times
   // learned-budget network weights (device), nullptr until loaded
   float* mlp_w = nullptr;
+  // batch plans (tiles, descriptors, captured graph), by plan key
+  es::BatchPlan* plans = nullptr;
+  hipStream_t capture_stream = nullptr;
 };
 
 namespace es {
@@ -108,6 +116,8 @@ enum Slot : int {
   kWsTotals,
   kWsTopk,
   kWsMisc,
+  kWsBatchT,
+  kWsBatchMisc,
   kWsCount
 };
 
@@ -138,6 +148,10 @@ es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const 
 // or by external ids (external_counts = true); M is indexed like the counts.
 es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
                        uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out);
+// Shared samples of a block of B sources: Rmax[k] pairs per internal node k,
+// meetings bucketed by T (ascending thresholds per node, stride B) into H[k * B + j].
+es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
+                               uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out);
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
                       double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1
@@ -147,6 +161,7 @@ es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, 
 es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                       double* val_out);
 es_status build_plan(es_ctx* ctx, const int32_t* off_host, int32_t n, SpmvPlan* plan);
+void free_batch_plans(es_ctx* ctx);
 void free_plan(SpmvPlan* plan);
 
 // host constants

@@ -203,6 +203,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
       WalkTotals h;
       ES_CHECK_HIP(ctx, hipMemcpy(&h, tot, sizeof(h), hipMemcpyDeviceToHost));
       s.pairs = h.total;
+      s.pairs_requested = h.total;
       s.active_nodes = h.n_active;
       s.meets = h.meets;
       s.philox_blocks = h.blocks;

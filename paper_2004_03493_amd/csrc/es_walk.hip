@@ -285,7 +285,9 @@ struct WalkArgs {
   const uint64_t* __restrict__ thr;
   int32_t tmax;
   WalkTotals* tot;
-  unsigned long long* __restrict__ M;
+  unsigned long long* __restrict__ M;  // per count index; with buckets: [index * B + bucket]
+  const uint64_t* __restrict__ T;      // buckets only: ascending thresholds of each index, stride B
+  int32_t B;
   uint64_t seed;
 };
 
@@ -301,6 +303,13 @@ __device__ __forceinline__ int walk_step(const int32_t* __restrict__ in_off, con
   return x == y ? 1 : 0;
 }
 
+// kBuckets = false: M[k] counts the meeting pairs of node k.
+// kBuckets = true (shared samples of a source block): a meeting pair r of node k
+// is counted in bucket j = #{b : T[k][b] <= r} of M[k * B + j], where T[k] holds
+// the block's per-source sample counts R_b(k) in ascending order; source b then
+// owns the meetings of buckets j <= #{b' : R_b'(k) < R_b(k)}, i.e. exactly the
+// meetings among its own pairs r < R_b(k).
+template <bool kBuckets>
 __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
   const int lane = threadIdx.x & 63;
   const uint64_t total = a.tot->total;
@@ -308,6 +317,8 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
   // meeting count held for node cnt_node, flushed when the lane moves on
   int32_t cnt_node = -1;
   unsigned long long cnt = 0;
+  int32_t cnt_bucket = 0;      // buckets only
+  uint64_t next_thr = 0;       // buckets only: first threshold above the cached bucket
   unsigned long long nblocks = 0, nsteps = 0;  // work counters for the roofline
   for (;;) {
     unsigned long long c0 = 0;
@@ -387,22 +398,45 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
       if (res != 0) {
         in_pair = false;
         if (res > 0) {
-          if (k == cnt_node) {
-            ++cnt;
-          } else {
-            if (cnt) {
-              atomicAdd(&a.M[cnt_node], cnt);
-              atomicAdd(&a.tot->meets, cnt);
+          if constexpr (!kBuckets) {
+            if (k == cnt_node) {
+              ++cnt;
+            } else {
+              if (cnt) {
+                atomicAdd(&a.M[cnt_node], cnt);
+                atomicAdd(&a.tot->meets, cnt);
+              }
+              cnt_node = k;
+              cnt = 1;
             }
-            cnt_node = k;
-            cnt = 1;
+          } else {
+            if (k == cnt_node && r < next_thr) {
+              ++cnt;
+            } else {
+              if (cnt) {
+                atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], cnt);
+                atomicAdd(&a.tot->meets, cnt);
+              }
+              const uint64_t* Tk = a.T + (int64_t)k * a.B;
+              int32_t lo = 0, hi = a.B;  // first threshold above r
+              while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (Tk[mid] <= r) lo = mid + 1;
+                else hi = mid;
+              }
+              cnt_bucket = lo;
+              next_thr = lo < a.B ? Tk[lo] : ~0ull;
+              cnt_node = k;
+              cnt = 1;
+            }
           }
         }
       }
     }
   }
   if (cnt) {
-    atomicAdd(&a.M[cnt_node], cnt);
+    if constexpr (kBuckets) atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], cnt);
+    else atomicAdd(&a.M[cnt_node], cnt);
     atomicAdd(&a.tot->meets, cnt);
   }
   // one atomic per wave for the work counters
@@ -443,8 +477,11 @@ es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const 
   return ES_OK;
 }
 
-es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
-                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out) {
+namespace {
+
+es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end, uint64_t seed,
+                     double c, unsigned long long* M, int64_t m_len, bool external_counts, const uint64_t* T,
+                     int32_t B, WalkTotals** totals_out) {
   const int32_t n = g->n;
   es_status st;
   ES_TRY(lifetime_table(ctx, c));
@@ -460,7 +497,7 @@ es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, 
   auto* prefix = (uint64_t*)workspace(ctx, kWsPrefix, sizeof(uint64_t) * ((size_t)n + 1), &st);
   if (!prefix) return st;
   zero_totals_kernel<<<1, 1, 0, ctx->stream>>>(tot);
-  zero_u64_kernel<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, (unsigned long long*)M);
+  zero_u64_kernel<<<ceil_div(m_len, 256), 256, 0, ctx->stream>>>(m_len, M);
   scan_count_kernel<<<nb, kScanThreads, 0, ctx->stream>>>(n, r_begin, r_end, bcnt, bsum, tot);
   scan_blocks_kernel<<<1, kScanThreads, 0, ctx->stream>>>(nb, bcnt, bsum, tot);
   scan_write_kernel<<<nb, kScanThreads, 0, ctx->stream>>>(n, r_begin, r_end, bcnt, bsum, tot, active, prefix);
@@ -475,14 +512,31 @@ es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, 
   a.thr = ctx->thr;
   a.tmax = ctx->tmax;
   a.tot = tot;
-  a.M = (unsigned long long*)M;
+  a.M = M;
+  a.T = T;
+  a.B = B;
   a.seed = seed;
   const int grid = ctx->num_cus * 8;
   if (ctx->ev_walk_begin) ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev_walk_begin, ctx->stream));
-  walk_pairs_kernel<<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  if (T) walk_pairs_kernel<true><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  else walk_pairs_kernel<false><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
   ES_CHECK_HIP(ctx, hipGetLastError());
   if (totals_out) *totals_out = tot;
   return ES_OK;
+}
+
+}  // namespace
+
+es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out) {
+  return walks_core(ctx, g, r_begin, r_end, seed, c, (unsigned long long*)M, g->n, external_counts, nullptr, 1,
+                    totals_out);
+}
+
+es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
+                               uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out) {
+  return walks_core(ctx, g, nullptr, Rmax, seed, c, (unsigned long long*)H, (int64_t)g->n * B, false, T, B,
+                    totals_out);
 }
 
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,

@@ -1,0 +1,155 @@
+"""GPU batches: many sources and uneven graphs in one pass.
+
+A batch must give every source the result of its own single-source query:
+identical walk and meeting counts (shared samples, bucketed per source) and
+s within float64 summation error; and the oracle's s within 1e-9.  Results may
+not depend on the tiling, on hipGraph replay, or on how queries are grouped.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import exactsim as ox
+from oracle.graph import OracleGraph
+
+pytestmark = pytest.mark.gpu
+
+C = 0.6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def es():
+    from paper_2004_03493_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(es):
+    c = es.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def graphs(es, ctx):
+    specs = [(2000,) + workloads.chung_lu(2000, 20000, 11),
+             (1 << 15,) + workloads.rmat(1 << 15, 500_000, 5),
+             (7000,) + workloads.rmat(7000, 35_000, 8)]
+    return [(es.Graph(ctx, n, s, d), OracleGraph(n, s, d)) for n, s, d in specs]
+
+
+def single(es, ctx, g, u, opts):
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = es.es_single_source(ctx, g, u, opts, s)
+    return s.cpu().numpy(), st
+
+
+def run_batch(es, ctx, gl, goq, srcs, opts, **kw):
+    outs = [torch.full((gl[g].n,), float("nan"), dtype=torch.float64, device="cuda") for g in goq]
+    st = es.es_batch(ctx, gl, goq, srcs, opts, outs, **kw)
+    return [o.cpu().numpy() for o in outs], st
+
+
+def pick(og, count, seed):
+    return [int(x) for x in workloads.pick_sources(og.n, og.dst, count, seed)]
+
+
+def test_batch_equals_single_source_and_oracle(es, ctx, graphs):
+    g, og = graphs[0]
+    srcs = pick(og, 10, 1)
+    opts = es.make_opts(C, 1e-4, 31, 1e-3)
+    say(f"  batch of {len(srcs)}")
+    outs, st = run_batch(es, ctx, [g], [0] * len(srcs), srcs, opts)
+    meets = pairs = 0
+    for u, s in zip(srcs, outs):
+        ref, st1 = single(es, ctx, g, u, opts)
+        meets += st1.meets
+        pairs += st1.pairs
+        assert np.abs(s - ref).max() <= 1e-13
+        q = ox.query(og, u, C, 1e-4, 31, 1e-3)
+        assert np.abs(s - q["s"]).max() <= 1e-9
+    assert st.meets == meets
+    assert st.pairs_requested == pairs
+    assert st.pairs <= pairs  # shared samples never exceed the per-source total
+
+
+def test_uneven_multi_graph_batch(es, ctx, graphs):
+    gl = [g for g, _ in graphs]
+    counts = [3, 70, 9]  # 70 splits into blocks of 64 and 6
+    goq, srcs = [], []
+    for gi, (cnt, (g, og)) in enumerate(zip(counts, graphs)):
+        s = pick(og, cnt, 10 + gi)
+        goq += [gi] * cnt
+        srcs += s
+    # interleave queries so that blocks are gathered by graph, not by position
+    order = np.random.default_rng(0).permutation(len(srcs))
+    goq = [goq[i] for i in order]
+    srcs = [srcs[i] for i in order]
+    opts = es.make_opts(C, 1e-6, 5, 1e-7)
+    say(f"  uneven batch of {len(srcs)} over {len(gl)} graphs")
+    outs, st = run_batch(es, ctx, gl, goq, srcs, opts)
+    meets = 0
+    for q in range(len(srcs)):
+        ref, st1 = single(es, ctx, gl[goq[q]], srcs[q], opts)
+        meets += st1.meets
+        assert np.abs(outs[q] - ref).max() <= 1e-13, q
+    assert st.meets == meets
+
+
+def test_batch_tilings_agree(es, ctx, graphs):
+    g, og = graphs[1]
+    srcs = pick(og, 12, 3)
+    opts = es.make_opts(C, 1e-6, 7, 1e-7)
+    base, st0 = run_batch(es, ctx, [g], [0] * 12, srcs, opts, autotune=False)
+    for w in (16, 32, 64):
+        for rows in (4, 32, 200):
+            say(f"  width={w} rows={rows}")
+            outs, st = run_batch(es, ctx, [g], [0] * 12, srcs, opts, autotune=False, force_width=w, force_rows=rows)
+            assert st.meets == st0.meets and st.pairs == st0.pairs
+            for a, b in zip(base, outs):
+                assert np.abs(a - b).max() <= 1e-13
+
+
+def test_batch_hip_graph_replays(es, ctx, graphs):
+    g, og = graphs[2]
+    opts = es.make_opts(C, 1e-4, 9, 1e-2)
+    for rep, seed in enumerate((1, 2, 3)):
+        srcs = pick(og, 8, seed)
+        say(f"  replay {rep}")
+        eager, st_e = run_batch(es, ctx, [g], [0] * 8, srcs, opts, autotune=False)
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        graph, st_g = run_batch(es, ctx, [g], [0] * 8, srcs, opts, autotune=False, use_hip_graph=True)
+        assert st_g.meets == st_e.meets
+        for a, b in zip(eager, graph):
+            assert np.array_equal(a, b)
+
+
+def test_batch_autotune_records_choice(es, ctx, graphs):
+    g, og = graphs[2]
+    srcs = pick(og, 20, 4)
+    opts = es.make_opts(C, 1e-4, 9, 1e-3)
+    run_batch(es, ctx, [g], [0] * 20, srcs, opts, autotune=True)
+    w, rows = es.es_batch_tuning(g, 20)
+    assert w in (32, 64) and rows > 0
+
+
+def test_batch_argument_errors(es, ctx, graphs):
+    g, og = graphs[0]
+    opts = es.make_opts(C, 1e-4, 1, 1e-3)
+    out = [torch.empty(g.n, dtype=torch.float64, device="cuda")]
+    with pytest.raises(es.EsError):
+        es.es_batch(ctx, [g], [1], [0], opts, out)
+    with pytest.raises(es.EsError):
+        es.es_batch(ctx, [g], [0], [g.n], opts, out)
+    with pytest.raises(es.EsError):
+        es.es_batch(ctx, [g], [0], [0], opts, out, force_width=12)
