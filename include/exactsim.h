@@ -205,6 +205,47 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
 es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                   double* val_out);
 
+/* ---- learned walk budget --------------------------------------------------
+ * Lemma 1 (Section 3.1) bounds the variance of s^L(j) by a sum over nodes k of
+ * pi_i(k)^2 pi_j(k)^2 D(k,k)(1 - D(k,k)) / rho(k); the paper then bounds the
+ * Bernoulli variance D(1-D) by 1 and allocates rho(k) ~ pi(k)^2 (Section 3.2).
+ * The learned allocation keeps that factor: a network (6 -> 64 -> 64 -> 1,
+ * ReLU, float32) predicts the meeting probability p(k) = 1 - D(k,k) in
+ * (0, c) from local features, v(k) = max(p(1-p), 1e-6), and
+ *   R(k) = ceil((R * (pi(k)*pi(k))) * (v(k) * S2/S1)),
+ *   S1 = sum Q(pi^2 v), S2 = sum Q(pi^2), Q(x) = round(x * 2^62) (exact int64
+ *   sums over the nodes that take samples),
+ * which keeps the pi^2 rule's total and gives every node with pi(k) > 0 at
+ * least one pair, so D^ stays unbiased.  Weights: float32 [es_mlp_num_params()]
+ * = W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Features per node: log1p d_in, log1p d_out, log1p of the mean and of the
+ * max in-degree of its in-neighbours, log1p(n pi(k)^2/sum pi^2), c/d_in. */
+
+int32_t es_mlp_num_params(void);
+/* feats: device float32 [n][6] by external id; pi: device float64 [n] (es_forward). */
+es_status es_mlp_features(es_ctx* ctx, const es_graph* g, const double* pi, double c, float* feats);
+/* p_out, v_out: device float32 [N] (either may be NULL): p and v of each row of feats. */
+es_status es_mlp_infer(es_ctx* ctx, const float* weights, const float* feats, int64_t N, double c, float* p_out,
+                       float* v_out);
+/* Training rows: feats [N][6], R, M device uint64 [N]: R(k) pairs of Algorithm 2
+ * of which M(k) met.  Loss: sum_k w_k BCE(y_k, p_k) / sum_k w_k with the
+ * observed meeting fraction y_k = M/R and weight w_k = min(R, 65536) (rows
+ * with R = 0 carry no weight).  grad: device float32 [num_params]; loss
+ * (host, nullable) receives the loss (synchronizes). */
+es_status es_mlp_grad(es_ctx* ctx, const float* weights, const float* feats, const uint64_t* R, const uint64_t* M,
+                      int64_t N, double c, float* grad, double* loss);
+/* `epochs` full-batch Adam steps (lr, betas 0.9 / 0.999, eps 1e-8) on that
+ * loss, updating weights (device) in place; losses (host float [epochs],
+ * nullable) gets the loss before each step (synchronizes). */
+es_status es_mlp_train(es_ctx* ctx, const float* feats, const uint64_t* R, const uint64_t* M, int64_t N, double c,
+                       int32_t epochs, float lr, float* weights, float* losses);
+/* Copy the weights into the context for ES_ALLOC_LEARNED (NULL: unload). */
+es_status es_mlp_load(es_ctx* ctx, const float* weights);
+/* The weighted allocation above with a given v (device float32 [n], external
+ * order): Rk device uint64 [n]. */
+es_status es_budget_weighted(es_ctx* ctx, const es_graph* g, const double* pi, const float* v, double R,
+                             int32_t exact_small_din, uint64_t* Rk);
+
 /* ---- batches ------------------------------------------------------------ */
 
 typedef struct {

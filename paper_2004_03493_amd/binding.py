@@ -35,6 +35,8 @@ SYMBOLS = (
     "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_degrees",
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
     "es_backward", "es_single_source", "es_topk", "es_batch", "es_batch_tuning",
+    "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
+    "es_budget_weighted",
 )
 
 
@@ -102,6 +104,13 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_batch": [P, P, i32, P, P, i32, ctypes.POINTER(QueryOpts), ctypes.POINTER(BatchOpts), P,
                      ctypes.POINTER(Stats)],
         "es_batch_tuning": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "es_mlp_num_params": [],
+        "es_mlp_features": [P, P, P, dbl, P],
+        "es_mlp_infer": [P, P, P, i64, dbl, P, P],
+        "es_mlp_grad": [P, P, P, P, P, i64, dbl, P, ctypes.POINTER(dbl)],
+        "es_mlp_train": [P, P, P, P, i64, dbl, i32, ctypes.c_float, P, P],
+        "es_mlp_load": [P, P],
+        "es_budget_weighted": [P, P, P, P, dbl, i32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -306,3 +315,49 @@ def es_batch_tuning(g: Graph, B: int):
     r = ctypes.c_int32()
     _check(load_library().es_batch_tuning(g.handle, B, ctypes.byref(w), ctypes.byref(r)))
     return w.value, r.value
+
+
+def es_mlp_num_params() -> int:
+    return int(load_library().es_mlp_num_params())
+
+
+def es_mlp_features(ctx: Context, g: Graph, pi, c: float, feats):
+    _check(load_library().es_mlp_features(ctx.handle, g.handle, _ptr(pi, torch.float64, g.n, "pi"), c,
+                                          _ptr(feats, torch.float32, 6 * g.n, "feats")), ctx)
+
+
+def es_mlp_infer(ctx: Context, weights, feats, N: int, c: float, p_out=None, v_out=None):
+    _check(load_library().es_mlp_infer(ctx.handle, _ptr(weights, torch.float32, es_mlp_num_params(), "weights"),
+                                       _ptr(feats, torch.float32, 6 * N, "feats"), N, c,
+                                       _ptr(p_out, torch.float32, N, "p_out"), _ptr(v_out, torch.float32, N, "v_out")),
+           ctx)
+
+
+def es_mlp_grad(ctx: Context, weights, feats, R, M, N: int, c: float, grad) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().es_mlp_grad(ctx.handle, _ptr(weights, torch.float32, es_mlp_num_params(), "weights"),
+                                      _ptr(feats, torch.float32, 6 * N, "feats"), _ptr(R, torch.uint64, N, "R"),
+                                      _ptr(M, torch.uint64, N, "M"), N, c,
+                                      _ptr(grad, torch.float32, es_mlp_num_params(), "grad"), ctypes.byref(loss)), ctx)
+    return loss.value
+
+
+def es_mlp_train(ctx: Context, feats, R, M, N: int, c: float, epochs: int, lr: float, weights):
+    import numpy as np
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(load_library().es_mlp_train(ctx.handle, _ptr(feats, torch.float32, 6 * N, "feats"),
+                                       _ptr(R, torch.uint64, N, "R"), _ptr(M, torch.uint64, N, "M"), N, c, epochs,
+                                       lr, _ptr(weights, torch.float32, es_mlp_num_params(), "weights"),
+                                       losses.ctypes.data), ctx)
+    return losses
+
+
+def es_mlp_load(ctx: Context, weights):
+    _check(load_library().es_mlp_load(ctx.handle, _ptr(weights, torch.float32, es_mlp_num_params(), "weights")),
+           ctx)
+
+
+def es_budget_weighted(ctx: Context, g: Graph, pi, v, R: float, exact_small_din: bool, Rk):
+    _check(load_library().es_budget_weighted(ctx.handle, g.handle, _ptr(pi, torch.float64, g.n, "pi"),
+                                             _ptr(v, torch.float32, g.n, "v"), R, int(exact_small_din),
+                                             _ptr(Rk, torch.uint64, g.n, "Rk")), ctx)

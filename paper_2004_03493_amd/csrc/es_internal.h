@@ -118,6 +118,12 @@ enum Slot : int {
   kWsMisc,
   kWsBatchT,
   kWsBatchMisc,
+  kWsFeat,
+  kWsVhat,
+  kWsMlpSums,
+  kWsMlpAcc,
+  kWsMlpGrad,
+  kWsMlpLoss,
   kWsCount
 };
 
@@ -152,6 +158,9 @@ es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, 
 // meetings bucketed by T (ascending thresholds per node, stride B) into H[k * B + j].
 es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
                                uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out);
+// Learned allocation (internal order): features, network, weighted budget.
+es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
+                                int32_t exact_small_din, uint64_t* Rk);
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
                       double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1

@@ -1,0 +1,470 @@
+// Learned walk budget: features, the 6-64-64-1 network (inference, gradient,
+// Adam), and the variance-weighted sample allocation.
+//
+// The variance bound of Lemma 1 (Section 3.1) keeps the Bernoulli variance
+// D(k,k)(1 - D(k,k)) of each pair before the paper bounds it by 1; under a fixed
+// total, the worst case over targets is smallest when R(k) is proportional to
+// pi(k)^2 D(1-D).  The network predicts the meeting probability p(k) = 1 - D(k,k)
+// from local degree features, v(k) = max(p(1-p), 1e-6), and
+//   R(k) = ceil((R * pi(k)^2) * (v(k) * S2 / S1)),
+//   S1 = sum Q(pi^2 v), S2 = sum Q(pi^2), Q(x) = round(x 2^62), exact int64 sums,
+// so the total matches the pi^2 rule and every node with pi(k) > 0 keeps at least
+// one pair: the estimator stays unbiased whatever the network predicts.
+//
+// All network arithmetic is float32 on the vector ALUs: at width 64 each
+// sample is a few thousand multiply-adds against weights held in LDS.
+#include <cmath>
+#include <vector>
+
+#include "es_internal.h"
+
+namespace es {
+namespace {
+
+constexpr int NF = 6, H = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = H * NF, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H, OFF_W3 = OFF_B2 + H,
+              OFF_B3 = OFF_W3 + H, NPARAM = OFF_B3 + 1;
+constexpr float V_FLOOR = 1e-6f;
+constexpr int kInferThreads = 256;
+constexpr int kGradThreads = 128;
+constexpr int kPad = H + 1;  // LDS row stride (conflict-free column access)
+constexpr uint64_t kWeightCap = 65536;  // a node's weight in the loss: min(R(k), cap)
+
+// ---- features ----------------------------------------------------------------
+
+// feats[v] for v in [0, n): k = to_int ? to_int[v] : v (internal id), pi indexed by v.
+__global__ void features_kernel(int32_t n, const int32_t* __restrict__ to_int, const int32_t* __restrict__ in_off,
+                                const int32_t* __restrict__ in_idx, const int32_t* __restrict__ din,
+                                const int32_t* __restrict__ out_off, const double* __restrict__ pi,
+                                const unsigned long long* __restrict__ pi2_sum, float c, float* __restrict__ F) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t k = to_int ? to_int[v] : (int32_t)v;
+  const int32_t d = din[k];
+  const int32_t dout = out_off[k + 1] - out_off[k];
+  int64_t s = 0;
+  int32_t mx = 0;
+  for (int32_t e = in_off[k]; e < in_off[k + 1]; ++e) {
+    const int32_t dd = din[in_idx[e]];
+    s += dd;
+    mx = dd > mx ? dd : mx;
+  }
+  const double p = pi[v];
+  const double tot = (double)(*pi2_sum) * 0x1p-62;
+  float* f = F + v * NF;
+  f[0] = log1pf((float)d);
+  f[1] = log1pf((float)dout);
+  f[2] = d > 0 ? log1pf((float)((double)s / (double)d)) : 0.0f;
+  f[3] = log1pf((float)mx);
+  f[4] = tot > 0.0 ? log1pf((float)((double)n * ((p * p) / tot))) : 0.0f;
+  f[5] = d > 0 ? c / (float)d : 0.0f;
+}
+
+// S[0] += Q(pi^2 v), S[1] += Q(pi^2) over nodes that take samples (v may be NULL: S[1] only)
+__global__ void weighted_sums_kernel(int32_t n, const double* __restrict__ pi, const float* __restrict__ v,
+                                     const int32_t* __restrict__ din, int32_t exact_small_din,
+                                     unsigned long long* __restrict__ S) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long a = 0, b = 0;
+  if (k < n) {
+    const double p = pi[k];
+    const bool take = p > 0.0 && (!exact_small_din || din[k] >= 2);
+    if (take) {
+      const double p2 = p * p;
+      if (v) a = (unsigned long long)(int64_t)rint((p2 * (double)v[k]) * 0x1p62);
+      b = (unsigned long long)(int64_t)rint(p2 * 0x1p62);
+    }
+  }
+  for (int m = 32; m > 0; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (a | b)) {
+    atomicAdd(&S[0], a);
+    atomicAdd(&S[1], b);
+  }
+}
+
+__global__ void vbar_kernel(const unsigned long long* __restrict__ S, double* __restrict__ vbar_inv) {
+  const int64_t s1 = (int64_t)S[0], s2 = (int64_t)S[1];
+  *vbar_inv = s1 > 0 ? (double)s2 / (double)s1 : -1.0;
+}
+
+// R(k) = ceil((R * (pi*pi)) * (v * vbar_inv)); plain pi^2 rule if vbar_inv < 0
+__global__ void budget_weighted_kernel(int32_t n, const double* __restrict__ pi, const float* __restrict__ v,
+                                       const int32_t* __restrict__ din, double R, int32_t exact_small_din,
+                                       const double* __restrict__ vbar_inv_p, uint64_t* __restrict__ Rk) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double p = pi[k];
+  const double vi = *vbar_inv_p;
+  double want = R * (p * p);
+  if (vi >= 0.0) want = want * ((double)v[k] * vi);
+  uint64_t r = (uint64_t)ceil(want);
+  if (!(p > 0.0)) r = 0;
+  if (exact_small_din && din[k] <= 1) r = 0;
+  Rk[k] = r;
+}
+
+__global__ void zero_sums(unsigned long long* S, int n) {
+  if (threadIdx.x < n) S[threadIdx.x] = 0ull;
+}
+
+// ---- network ------------------------------------------------------------------
+
+__device__ __forceinline__ void load_weights(const float* __restrict__ w, float* sw) {
+  for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) sw[i] = w[i];
+}
+
+// p_out (nullable): c * sigmoid(z); v_out (nullable): max(p(1-p), V_FLOOR)
+__global__ __launch_bounds__(kInferThreads) void infer_kernel(int64_t N, const float* __restrict__ F,
+                                                              const float* __restrict__ w, float c,
+                                                              float* __restrict__ p_out, float* __restrict__ v_out) {
+  __shared__ float sw[NPARAM];
+  load_weights(w, sw);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float x[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) x[j] = F[i * NF + j];
+  float h1[H];
+#pragma unroll
+  for (int a = 0; a < H; ++a) {
+    float s = sw[OFF_B1 + a];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) s += sw[OFF_W1 + a * NF + j] * x[j];
+    h1[a] = s > 0.0f ? s : 0.0f;
+  }
+  float z = sw[OFF_B3];
+  for (int a = 0; a < H; ++a) {
+    float s = sw[OFF_B2 + a];
+#pragma unroll
+    for (int j = 0; j < H; ++j) s += sw[OFF_W2 + a * H + j] * h1[j];
+    z += sw[OFF_W3 + a] * (s > 0.0f ? s : 0.0f);
+  }
+  const float p = c / (1.0f + expf(-z));
+  if (p_out) p_out[i] = p;
+  if (v_out) {
+    const float vv = p * (1.0f - p);
+    v_out[i] = vv > V_FLOOR ? vv : V_FLOOR;
+  }
+}
+
+// Unnormalised gradient of sum_i w_i BCE(y_i, p_i) and the loss sum, accumulated
+// atomically into grad[NPARAM] and acc[0] (loss), acc[1] (sum of weights).
+// Labels: y = M(k)/R(k), the observed meeting fraction of R(k) pairs, weight
+// min(R(k), cap) (rows with R(k) = 0 carry no weight).
+__global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const float* __restrict__ F,
+                                                            const uint64_t* __restrict__ Rn,
+                                                            const uint64_t* __restrict__ Mn,
+                                                            const float* __restrict__ w, float c,
+                                                            float* __restrict__ grad, double* __restrict__ acc) {
+  __shared__ float sw[NPARAM];
+  __shared__ float H1[kGradThreads * kPad];   // h1, later dh1
+  __shared__ float D2[kGradThreads * kPad];   // dh2 (pre-activation gradient of layer 2)
+  __shared__ float G3[kGradThreads * kPad];   // gz * h2
+  __shared__ float XS[kGradThreads * NF];
+  __shared__ float GZ[kGradThreads];
+  __shared__ double red[2][kGradThreads / 64];
+  load_weights(w, sw);
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kGradThreads + t;
+  const bool live = i < N;
+  float x[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    x[j] = live ? F[i * NF + j] : 0.0f;
+    XS[t * NF + j] = x[j];
+  }
+  __syncthreads();
+  // each thread works on its own LDS rows (stride kPad: conflict-free)
+  float* h1 = H1 + t * kPad;
+  float* d2 = D2 + t * kPad;
+  float* g3 = G3 + t * kPad;
+  for (int a = 0; a < H; ++a) {
+    float s = sw[OFF_B1 + a];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) s += sw[OFF_W1 + a * NF + j] * x[j];
+    h1[a] = s > 0.0f ? s : 0.0f;
+  }
+  float z = sw[OFF_B3];
+  for (int a = 0; a < H; ++a) {
+    float s = sw[OFF_B2 + a];
+#pragma unroll 8
+    for (int j = 0; j < H; ++j) s += sw[OFF_W2 + a * H + j] * h1[j];
+    d2[a] = s;  // pre-activation, turned into its gradient below
+    z += sw[OFF_W3 + a] * (s > 0.0f ? s : 0.0f);
+  }
+  const float sig = 1.0f / (1.0f + expf(-z));
+  const float p = c * sig;
+  float gz = 0.0f;
+  double lsum = 0.0, wsum = 0.0;
+  if (live && Rn[i] > 0) {
+    const uint64_t rr = Rn[i];
+    const float yy = (float)((double)Mn[i] / (double)rr);
+    const float ww = (float)(rr < kWeightCap ? rr : kWeightCap);
+    // d/dz of w * BCE(y, c sigmoid(z)) = w (1 - p/c) (-y + (1 - y) p/(1 - p))
+    gz = ww * (1.0f - p / c) * (-yy + (1.0f - yy) * p / (1.0f - p));
+    lsum = -(double)ww * ((double)yy * log((double)p) + (1.0 - (double)yy) * log1p(-(double)p));
+    wsum = ww;
+  }
+  GZ[t] = gz;
+  for (int a = 0; a < H; ++a) {
+    const float a2 = d2[a];
+    g3[a] = a2 > 0.0f ? gz * a2 : 0.0f;
+    d2[a] = a2 > 0.0f ? gz * sw[OFF_W3 + a] : 0.0f;
+  }
+  for (int m = 32; m > 0; m >>= 1) {
+    lsum += __shfl_xor(lsum, m, 64);
+    wsum += __shfl_xor(wsum, m, 64);
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = lsum;
+    red[1][t >> 6] = wsum;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double l = 0.0, ws = 0.0;
+    for (int q = 0; q < kGradThreads / 64; ++q) {
+      l += red[0][q];
+      ws += red[1][q];
+    }
+    atomicAdd(&acc[0], l);
+    atomicAdd(&acc[1], ws);
+  }
+  // dW2[a][j] = sum_t D2[t][a] H1[t][j]; thread t owns entries e = t, t + 128, ...
+  for (int e = t; e < H * H; e += kGradThreads) {
+    const int a = e / H, j = e - a * H;
+    float s = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) s += D2[q * kPad + a] * H1[q * kPad + j];
+    atomicAdd(&grad[OFF_W2 + e], s);
+  }
+  if (t < H) {
+    float sb2 = 0.0f, sw3 = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) {
+      sb2 += D2[q * kPad + t];
+      sw3 += G3[q * kPad + t];
+    }
+    atomicAdd(&grad[OFF_B2 + t], sb2);
+    atomicAdd(&grad[OFF_W3 + t], sw3);
+  } else if (t == H) {
+    float s = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) s += GZ[q];
+    atomicAdd(&grad[OFF_B3], s);
+  }
+  __syncthreads();
+  // dh1[j] = [h1_j > 0] sum_a W2[a][j] D2[t][a], written over G3
+  for (int j = 0; j < H; ++j) {
+    float s = 0.0f;
+#pragma unroll 8
+    for (int a = 0; a < H; ++a) s += sw[OFF_W2 + a * H + j] * d2[a];
+    g3[j] = h1[j] > 0.0f ? s : 0.0f;
+  }
+  __syncthreads();
+  for (int e = t; e < H * NF; e += kGradThreads) {
+    const int a = e / NF, j = e - a * NF;
+    float s = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) s += G3[q * kPad + a] * XS[q * NF + j];
+    atomicAdd(&grad[OFF_W1 + e], s);
+  }
+  if (t < H) {
+    float s = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) s += G3[q * kPad + t];
+    atomicAdd(&grad[OFF_B1 + t], s);
+  }
+}
+
+__global__ void zero_f32(int n, float* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+__global__ void zero_f64(int n, double* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// grad /= sum of weights
+__global__ void normalise_kernel(float* __restrict__ grad, const double* __restrict__ acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NPARAM && acc[1] > 0.0) grad[i] = (float)((double)grad[i] / acc[1]);
+}
+
+// Adam (Kingma and Ba, 2015) on the normalised gradient
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ grad, float* __restrict__ m,
+                            float* __restrict__ v, const double* __restrict__ acc, float lr, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPARAM) return;
+  const float g = acc[1] > 0.0 ? (float)((double)grad[i] / acc[1]) : 0.0f;
+  const float mi = 0.9f * m[i] + 0.1f * g;
+  const float vi = 0.999f * v[i] + 0.001f * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+__global__ void record_loss(const double* __restrict__ acc, float* __restrict__ out) {
+  *out = acc[1] > 0.0 ? (float)(acc[0] / acc[1]) : 0.0f;
+}
+
+bool valid_c(double c) { return c > 0.0 && c <= 0.99; }
+
+}  // namespace
+
+// Learned budget inside a query (internal node order): features, inference,
+// exact weighted sums, then R(k).
+es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
+                                int32_t exact_small_din, uint64_t* Rk) {
+  const int32_t n = g->n;
+  es_status st;
+  auto* F = (float*)workspace(ctx, kWsFeat, sizeof(float) * NF * (size_t)n, &st);
+  if (!F) return st;
+  auto* v = (float*)workspace(ctx, kWsVhat, sizeof(float) * (size_t)n + 64, &st);
+  if (!v) return st;
+  auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
+  if (!S) return st;
+  double* vbar = (double*)(S + 4);
+  const int tb = 256;
+  // sum of pi^2 over all nodes for the pi^2-mass feature
+  zero_sums<<<1, 64, 0, ctx->stream>>>(S, 4);
+  weighted_sums_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, nullptr, g->din_int, 0, S + 2);
+  features_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, nullptr, g->in_off, g->in_idx, g->din_int, g->out_off,
+                                                           pi, S + 3, (float)c, F);
+  infer_kernel<<<ceil_div(n, kInferThreads), kInferThreads, 0, ctx->stream>>>(n, F, ctx->mlp_w, (float)c, nullptr, v);
+  weighted_sums_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, v, g->din_int, exact_small_din, S);
+  vbar_kernel<<<1, 1, 0, ctx->stream>>>(S, vbar);
+  budget_weighted_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, v, g->din_int, R, exact_small_din, vbar, Rk);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+}  // namespace es
+
+using namespace es;
+
+extern "C" {
+
+es_status es_mlp_features(es_ctx* ctx, const es_graph* g, const double* pi, double c, float* feats) {
+  if (!ctx || !g || !pi || !feats) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
+  if (!S) return st;
+  const int tb = 256;
+  zero_sums<<<1, 64, 0, ctx->stream>>>(S, 4);
+  weighted_sums_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, nullptr, g->din_ext, 0, S + 2);
+  features_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, g->int_of, g->in_off, g->in_idx, g->din_int,
+                                                              g->out_off, pi, S + 3, (float)c, feats);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status es_mlp_infer(es_ctx* ctx, const float* weights, const float* feats, int64_t N, double c, float* p_out,
+                       float* v_out) {
+  if (!ctx || !weights || (!feats && N > 0) || N < 0 || (!p_out && !v_out)) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  if (N == 0) return ES_OK;
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  infer_kernel<<<(unsigned)((N + kInferThreads - 1) / kInferThreads), kInferThreads, 0, ctx->stream>>>(
+      N, feats, weights, (float)c, p_out, v_out);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status es_mlp_grad(es_ctx* ctx, const float* weights, const float* feats, const uint64_t* R, const uint64_t* M,
+                      int64_t N, double c, float* grad, double* loss) {
+  if (!ctx || !weights || !feats || !R || !M || N < 1 || !grad) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* acc = (double*)workspace(ctx, kWsMlpAcc, 64, &st);
+  if (!acc) return st;
+  zero_f32<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(NPARAM, grad);
+  zero_f64<<<1, 64, 0, ctx->stream>>>(2, acc);
+  grad_kernel<<<(unsigned)((N + kGradThreads - 1) / kGradThreads), kGradThreads, 0, ctx->stream>>>(
+      N, feats, R, M, weights, (float)c, grad, acc);
+  normalise_kernel<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(grad, acc);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  if (loss) {
+    double h[2];
+    ES_CHECK_HIP(ctx, hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *loss = h[1] > 0 ? h[0] / h[1] : 0.0;
+  }
+  return ES_OK;
+}
+
+es_status es_mlp_train(es_ctx* ctx, const float* feats, const uint64_t* R, const uint64_t* M, int64_t N, double c,
+                       int32_t epochs, float lr, float* weights, float* losses) {
+  if (!ctx || !feats || !R || !M || N < 1 || epochs < 1 || !(lr > 0.0f) || !weights) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* grad = (float*)workspace(ctx, kWsMlpGrad, sizeof(float) * 3 * NPARAM, &st);
+  if (!grad) return st;
+  float* m = grad + NPARAM;
+  float* v = grad + 2 * NPARAM;
+  auto* acc = (double*)workspace(ctx, kWsMlpAcc, 64, &st);
+  if (!acc) return st;
+  auto* dl = (float*)workspace(ctx, kWsMlpLoss, sizeof(float) * (size_t)epochs, &st);
+  if (!dl) return st;
+  zero_f32<<<ceil_div(3 * NPARAM, 256), 256, 0, ctx->stream>>>(3 * NPARAM, grad);
+  const unsigned gblocks = (unsigned)((N + kGradThreads - 1) / kGradThreads);
+  double b1t = 1.0, b2t = 1.0;
+  for (int32_t ep = 0; ep < epochs; ++ep) {
+    b1t *= 0.9;
+    b2t *= 0.999;
+    zero_f32<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(NPARAM, grad);
+    zero_f64<<<1, 64, 0, ctx->stream>>>(2, acc);
+    grad_kernel<<<gblocks, kGradThreads, 0, ctx->stream>>>(N, feats, R, M, weights, (float)c, grad, acc);
+    record_loss<<<1, 1, 0, ctx->stream>>>(acc, dl + ep);
+    adam_kernel<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(weights, grad, m, v, acc, lr, (float)(1.0 - b1t),
+                                                                 (float)(1.0 - b2t));
+  }
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  if (losses) {
+    ES_CHECK_HIP(ctx, hipMemcpyAsync(losses, dl, sizeof(float) * epochs, hipMemcpyDeviceToHost, ctx->stream));
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return ES_OK;
+}
+
+es_status es_mlp_load(es_ctx* ctx, const float* weights) {
+  if (!ctx) return ES_EINVAL;
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  if (!weights) {
+    ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ES_CHECK_HIP(ctx, hipFree(ctx->mlp_w));
+    ctx->mlp_w = nullptr;
+    return ES_OK;
+  }
+  if (!ctx->mlp_w) ES_CHECK_HIP(ctx, hipMalloc(&ctx->mlp_w, sizeof(float) * NPARAM));
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(ctx->mlp_w, weights, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, ctx->stream));
+  return ES_OK;
+}
+
+es_status es_budget_weighted(es_ctx* ctx, const es_graph* g, const double* pi, const float* v, double R,
+                             int32_t exact_small_din, uint64_t* Rk) {
+  if (!ctx || !g || !pi || !v || !Rk) return ES_EINVAL;
+  if (!(R > 0.0)) return fail(ctx, ES_EINVAL, "R=%g must be positive", R);
+  if (R + (double)g->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
+  if (!S) return st;
+  double* vbar = (double*)(S + 4);
+  const int tb = 256;
+  zero_sums<<<1, 64, 0, ctx->stream>>>(S, 2);
+  weighted_sums_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, v, g->din_ext, exact_small_din, S);
+  vbar_kernel<<<1, 1, 0, ctx->stream>>>(S, vbar);
+  budget_weighted_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, v, g->din_ext, R, exact_small_din, vbar,
+                                                                     Rk);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+int32_t es_mlp_num_params(void) { return NPARAM; }
+
+}  // extern "C"

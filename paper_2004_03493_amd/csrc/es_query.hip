@@ -176,8 +176,10 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     if (!Rk) return st;
     auto* M = (uint64_t*)workspace(ctx, kWsM, sizeof(uint64_t) * (size_t)n, &st);
     if (!M) return st;
-    if (o->alloc == ES_ALLOC_LEARNED) return fail(ctx, ES_EUNSUPPORTED, "learned allocation not built");
-    ES_TRY(launch_budget(ctx, g, pi, g->din_int, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
+    if (o->alloc == ES_ALLOC_LEARNED)
+      ES_TRY(launch_learned_budget(ctx, g, pi, R, o->c, o->exact_small_din, Rk));
+    else
+      ES_TRY(launch_budget(ctx, g, pi, g->din_int, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
     ctx->ev_walk_begin = ev[2];  // recorded between the sample-space scan and the walk kernel
     const es_status ws = launch_walks(ctx, g, nullptr, Rk, o->seed, o->c, M, false, &tot);
     ctx->ev_walk_begin = nullptr;

@@ -1,0 +1,201 @@
+"""GPU learned walk budget: features, network, gradient, training, allocation,
+and what the trained network gains over the pi^2 allocation."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import exactsim as ox
+from oracle import mlp
+from oracle import simrank as sr
+from oracle.graph import OracleGraph
+
+pytestmark = pytest.mark.gpu
+
+C = 0.6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def es():
+    from paper_2004_03493_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(es):
+    c = es.Context(0)
+    yield c
+    c.close()
+
+
+def graph_pair(es, ctx, n, src, dst):
+    return es.Graph(ctx, n, src, dst), OracleGraph(n, src, dst)
+
+
+@pytest.fixture(scope="module")
+def cl2k(es, ctx):
+    return graph_pair(es, ctx, 2000, *workloads.chung_lu(2000, 20000, 11))
+
+
+@pytest.fixture(scope="module")
+def rmat32k(es, ctx):
+    return graph_pair(es, ctx, 1 << 15, *workloads.rmat(1 << 15, 500_000, 5))
+
+
+def weights_tensor(theta):
+    return torch.as_tensor(np.asarray(theta, dtype=np.float32)).cuda()
+
+
+def forward_pi(es, ctx, g, u, eps=1e-4):
+    L = ox.num_levels(C, eps)
+    lv = torch.empty((L + 1) * g.n, dtype=torch.float64, device="cuda")
+    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_forward(ctx, g, u, C, L, lv, pi)
+    return pi
+
+
+@pytest.mark.parametrize("which", ["cl2k", "rmat32k"])
+def test_features_match_oracle(es, ctx, which, request):
+    g, og = request.getfixturevalue(which)
+    u = int(np.argmax(og.din))
+    pi = forward_pi(es, ctx, g, u)
+    F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
+    es.es_mlp_features(ctx, g, pi, C, F)
+    _, ref_pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
+    ref = mlp.features(og, ref_pi, C)
+    got = F.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 2e-6 * (1 + np.abs(ref)))
+
+
+def test_inference_matches_oracle(es, ctx):
+    rng = np.random.default_rng(3)
+    X = rng.normal(0, 1.5, (5000, 6)).astype(np.float32)
+    theta = mlp.init_params(11)
+    p = torch.empty(5000, dtype=torch.float32, device="cuda")
+    v = torch.empty(5000, dtype=torch.float32, device="cuda")
+    es.es_mlp_infer(ctx, weights_tensor(theta), torch.as_tensor(X).cuda(), 5000, C, p, v)
+    ref_p, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64), C)
+    assert np.abs(p.cpu().numpy() - ref_p).max() <= 1e-5 * C
+    assert np.abs(v.cpu().numpy() - mlp.predict_variance(theta.astype(np.float64), X.astype(np.float64), C)).max() <= 2e-6
+
+
+def test_gradient_matches_oracle(es, ctx):
+    rng = np.random.default_rng(5)
+    N = 3000  # several 128-row tiles and a ragged tail
+    X = rng.normal(0, 1.0, (N, 6)).astype(np.float32)
+    R = rng.integers(0, 100000, N).astype(np.uint64)
+    R[:50] = 0
+    M = (R.astype(np.float64) * rng.uniform(0, C, N)).astype(np.uint64)
+    theta = mlp.init_params(12)
+    grad = torch.empty(mlp.NPARAM, dtype=torch.float32, device="cuda")
+    loss = es.es_mlp_grad(ctx, weights_tensor(theta), torch.as_tensor(X).cuda(), torch.as_tensor(R).cuda(),
+                          torch.as_tensor(M).cuda(), N, C, grad)
+    y, w = mlp.labels(R, M)
+    ref_g = mlp.grad(theta.astype(np.float64), X.astype(np.float64), y, w, C)
+    ref_l = mlp.loss(theta.astype(np.float64), X.astype(np.float64), y, w, C)
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(loss - ref_l) <= 1e-5 * abs(ref_l)
+    assert np.linalg.norm(g - ref_g) <= 1e-4 * np.linalg.norm(ref_g)
+
+
+def test_weighted_budget_bitwise(es, ctx, rmat32k):
+    g, og = rmat32k
+    u = int(np.argmax(og.din))
+    pi = forward_pi(es, ctx, g, u)
+    v = np.random.default_rng(8).uniform(1e-6, 0.25, g.n).astype(np.float32)
+    R = ox.total_samples(g.n, C, 1e-4, 1e-2)
+    for small in (True, False):
+        Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+        es.es_budget_weighted(ctx, g, pi, torch.as_tensor(v).cuda(), R, small, Rk)
+        _, ref_pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
+        assert np.array_equal(Rk.cpu().numpy(), mlp.budget_weighted(ref_pi, og.din, R, v, small))
+
+
+@pytest.fixture(scope="module")
+def trained(es, ctx):
+    """Network trained on the GPU from the method's own walk estimates on
+    training graphs (none of them the evaluation graph)."""
+    from paper_2004_03493_amd import learned
+    Fs, Rs, Ms = [], [], []
+    specs = [(2000,) + workloads.chung_lu(2000, 20000, 101), (3000,) + workloads.chung_lu(3000, 24000, 102),
+             (1 << 14,) + workloads.rmat(1 << 14, 200_000, 103)]
+    for i, (n, s, d) in enumerate(specs):
+        g = es.Graph(ctx, n, s, d)
+        u = int(workloads.pick_sources(n, d, 1, 7 + i)[0])
+        F, R, M = learned.collect(ctx, g, u, C, 1e-4, 4000, 1000 + i)
+        Fs.append(F); Rs.append(R); Ms.append(M)
+    F = torch.cat(Fs); R = torch.cat(Rs); M = torch.cat(Ms)
+    say(f"  training rows {F.shape[0]}")
+    w, losses = learned.train(ctx, F, R, M, C, epochs=600, lr=3e-3, seed=7)
+    return w, losses, (F, R, M)
+
+
+def test_training_reduces_loss(es, ctx, trained):
+    w, losses, (F, R, M) = trained
+    assert losses[-1] < 0.9 * losses[0]
+    # the oracle's loss of the trained weights agrees with the GPU's last value
+    y, wt = mlp.labels(R.cpu().numpy(), M.cpu().numpy())
+    ref = mlp.loss(w.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), y, wt, C)
+    assert abs(ref - losses[-1]) <= 2e-2 * ref
+
+
+def test_trained_network_predicts_meeting_probability(es, ctx, trained, cl2k):
+    w, _, _ = trained
+    g, og = cl2k
+    S = sr.power_method(og, C, 60)
+    p_exact = 1 - sr.exact_diagonal(og, S, C)
+    pi = forward_pi(es, ctx, g, 0)
+    F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
+    es.es_mlp_features(ctx, g, pi, C, F)
+    p = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    es.es_mlp_infer(ctx, w, F, g.n, C, p, None)
+    keep = og.din >= 2
+    corr = np.corrcoef(p.cpu().numpy()[keep], p_exact[keep])[0, 1]
+    say(f"  corr(p_hat, p) = {corr:.3f}")
+    assert corr > 0.9
+
+
+def test_learned_query_accuracy_and_budget(es, ctx, trained, cl2k):
+    w, _, _ = trained
+    g, og = cl2k
+    S = sr.power_method(og, C, 60)
+    es.es_mlp_load(ctx, w)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eps = 1e-4
+    st_l = es.es_single_source(ctx, g, 0, es.make_opts(C, eps, 5, 1e-2, alloc=es.ES_ALLOC_LEARNED), s)
+    err = sr.max_error(s.cpu().numpy(), S[:, 0])
+    st_p = es.es_single_source(ctx, g, 0, es.make_opts(C, eps, 5, 1e-2), s)
+    say(f"  learned pairs {st_l.pairs} pi2 pairs {st_p.pairs} err {err:.2e}")
+    assert err <= eps
+    assert abs(st_l.pairs - st_p.pairs) <= 0.01 * st_p.pairs + g.n
+
+
+def test_learned_allocation_gains_over_pi2(es, ctx, trained, cl2k):
+    """At equal total pairs the learned allocation has a smaller MaxError than
+    the pi^2 allocation against the Power Method (mean over seeds and sources)."""
+    w, _, _ = trained
+    g, og = cl2k
+    S = sr.power_method(og, C, 60)
+    es.es_mlp_load(ctx, w)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eps = 1e-4
+    e_l, e_p, p_l, p_p = [], [], 0, 0
+    for u in (0, 5, 50, 300):
+        for seed in range(8):
+            st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, 200 + seed, 1e-3, alloc=es.ES_ALLOC_LEARNED), s)
+            e_l.append(sr.max_error(s.cpu().numpy(), S[:, u]))
+            p_l += st.pairs
+            st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, 200 + seed, 1e-3), s)
+            e_p.append(sr.max_error(s.cpu().numpy(), S[:, u]))
+            p_p += st.pairs
+    ratio = np.mean(e_p) / np.mean(e_l)
+    say(f"  MaxError pi2 {np.mean(e_p):.3e} learned {np.mean(e_l):.3e} ratio {ratio:.2f}; pairs {p_p} vs {p_l}")
+    assert abs(p_l - p_p) <= 0.01 * p_p + 32 * g.n
+    assert ratio > 1.15
