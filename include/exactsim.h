@@ -166,14 +166,15 @@ es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, 
  * of meeting pairs among pairs r in [r_begin(k), r_end(k)) of sqrt(c)-walk
  * pairs from v_k (r_begin: device uint64 [n] or NULL for 0; r_end: device
  * uint64 [n], usually R(k)).  Pair r of node k draws its randomness from
- * Philox4x64-10 with key (seed, 0) and counter (k, r, j, 0), j = 0, 1, ...:
- * block 0 word 0 sets the joint lifetime T (Pr[T >= t] = c^t), words 1-2
- * move the walks at step 1, block j words 0-1 at step 2j and words 2-3 at
- * step 2j+1; a walk moves to in-neighbour floor(w * d_in / 2^64) of its
- * node in ascending id order, a walk on a node without in-neighbours ends
- * the pair, and the pair meets when both walks stand on the same node after
- * the same step t >= 1.  Because each pair is a pure function of (seed, k, r),
- * any split of the sample ranges gives the same counts.
+ * Philox4x64-10 under key (seed, 0): its joint lifetime T (Pr[T >= t] = c^t,
+ * inverse transform against floor(c^t 2^64)) from word r mod 4 of the block
+ * with counter (k, floor(r/4), 0, 1), and the words that move both walks at
+ * step t from the block with counter (k, r, floor((t-1)/2), 0), words 0-1 at
+ * odd t and 2-3 at even t.  A walk moves to in-neighbour floor(w * d_in / 2^64)
+ * of its node in ascending id order, a walk on a node without in-neighbours
+ * ends the pair, and the pair meets when both walks stand on the same node
+ * after the same step t >= 1.  Because each pair is a pure function of
+ * (seed, k, r), any split of the sample ranges gives the same counts.
  * Errors: ES_EINVAL (c outside (0, 0.99]), ES_EOVERFLOW (total >= 2^63). */
 es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
                         uint64_t seed, double c, uint64_t* M);

@@ -9,22 +9,21 @@
  * with the HIP library; both implement the same published random number
  * generator and the same sampling rule, written separately.
  *
- * Sampling rule for pair r of node k (all integers unsigned 64-bit):
- *
- *   block(j) = Philox4x64-10(key = (seed, 0), counter = (k, r, j, 0)), four
- *              64-bit words b_j[0..3]  (Salmon, Moraes, Dror, Shaw: "Parallel
- *              random numbers: as easy as 1, 2, 3", SC 2011; 10 rounds).
+ * Sampling rule for pair r of node k (all integers unsigned 64-bit), with
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011; 10 rounds) under key (seed, 0):
  *
  *   Two independent sqrt(c)-walks can meet at step t only if both are still
  *   walking at step t; that happens with probability sqrt(c)^t * sqrt(c)^t =
- *   c^t.  The pair's joint lifetime T is drawn from b_0[0] by inverse
- *   transform: T = #{ t >= 1 : b_0[0] < thr[t] }, thr[t] = floor(c^t * 2^64)
- *   with c^t formed by repeated double multiplication, so Pr[T >= t] = c^t
- *   to within double rounding.
+ *   c^t.  The pair's joint lifetime T is drawn by inverse transform from the
+ *   word u = Philox(counter (k, floor(r/4), 0, 1))[r mod 4] (one block serves
+ *   four consecutive pairs): T = #{ t >= 1 : u < thr[t] }, thr[t] =
+ *   floor(c^t * 2^64) with c^t formed by repeated double multiplication, so
+ *   Pr[T >= t] = c^t to within double rounding.
  *
- *   The words that move the walks at step t are (wx, wy) = (b_0[1], b_0[2])
- *   for t = 1, (b_j[0], b_j[1]) for even t = 2j, (b_j[2], b_j[3]) for odd
- *   t = 2j + 1 >= 3.
+ *   The words that move the walks at step t come from the block
+ *   b_j = Philox(counter (k, r, j, 0)) with j = floor((t-1)/2):
+ *   (wx, wy) = (b_j[0], b_j[1]) for odd t, (b_j[2], b_j[3]) for even t.
  *
  *   Both walks start at v_k.  For t = 1..T: if either walk sits on a node
  *   with no in-neighbour it cannot move and the pair ends without meeting;
@@ -99,28 +98,21 @@ int oracle_lifetime_table(double c, uint64_t* thr, int cap) {
 int oracle_walk_pair(const int64_t* in_off, const int32_t* in_idx, uint64_t seed, const uint64_t* thr,
                      int tmax, uint64_t k, uint64_t r) {
   const uint64_t key[2] = {seed, 0};
-  uint64_t b[4];
-  uint64_t ctr[4] = {k, r, 0, 0};
-  oracle_philox4x64_10(ctr, key, b);
+  uint64_t life[4];
+  const uint64_t life_ctr[4] = {k, r / 4, 0, 1};
+  oracle_philox4x64_10(life_ctr, key, life);
+  const uint64_t u = life[r % 4];
   int T = 0;
-  while (T < tmax && b[0] < thr[T + 1]) ++T;
+  while (T < tmax && u < thr[T + 1]) ++T;
   uint64_t x = k, y = k;
+  uint64_t b[4];
   for (int t = 1; t <= T; ++t) {
-    uint64_t wx, wy;
-    if (t == 1) {
-      wx = b[1];
-      wy = b[2];
-    } else {
-      if (t % 2 == 0) {
-        ctr[2] = (uint64_t)(t / 2);
-        oracle_philox4x64_10(ctr, key, b);
-        wx = b[0];
-        wy = b[1];
-      } else {
-        wx = b[2];
-        wy = b[3];
-      }
+    if (t % 2 == 1) {
+      const uint64_t ctr[4] = {k, r, (uint64_t)((t - 1) / 2), 0};
+      oracle_philox4x64_10(ctr, key, b);
     }
+    const uint64_t wx = (t % 2 == 1) ? b[0] : b[2];
+    const uint64_t wy = (t % 2 == 1) ? b[1] : b[3];
     uint64_t dx = (uint64_t)(in_off[x + 1] - in_off[x]);
     uint64_t dy = (uint64_t)(in_off[y + 1] - in_off[y]);
     if (dx == 0 || dy == 0) return 0;

@@ -4,8 +4,10 @@
 // Walk pairs (Algorithm 2): every node's pairs are laid end to end in one
 // 64-bit sample space [0, sum_k R(k)); a persistent grid takes fixed-size
 // chunks of it from a queue, each lane walking its own run of consecutive
-// samples.  A lane whose pair ends starts its next pair in the same loop
-// iteration, so lanes stay busy while pair lengths vary.
+// samples.  Every loop iteration a lane draws exactly one Philox block: the
+// lifetime block of its next four pairs, or the movement block of two steps of
+// its current pair; pairs whose lifetime is zero end without any block, so
+// lanes stay busy while pair lengths vary.
 // Diagonal (Algorithm 2, Algorithm 3 lines 1-4): D^(k) = (R(k) - M(k)) / R(k).
 #include <cmath>
 
@@ -20,8 +22,9 @@ constexpr int kScanPer = 4;
 constexpr int kScanBlock = kScanThreads * kScanPer;  // nodes per scan block
 
 constexpr int kWalkThreads = 256;
-constexpr int kWalkPerLane = 64;                     // samples per lane per chunk
-constexpr uint64_t kWalkChunk = 64ull * kWalkPerLane;
+constexpr uint64_t kWalkMinRun = 16;    // samples per lane per chunk, lower and upper bound
+constexpr uint64_t kWalkMaxRun = 1024;
+constexpr int kLifeRegs = 8;            // lifetime thresholds kept in registers
 
 __global__ void budget_kernel(int32_t n, const double* __restrict__ pi, const int32_t* __restrict__ din_arr,
                               double R, int32_t alloc, int32_t exact_small_din, const float* __restrict__ vhat,
@@ -303,33 +306,73 @@ __device__ __forceinline__ int walk_step(const int32_t* __restrict__ in_off, con
   return x == y ? 1 : 0;
 }
 
+// Sum the per-lane work counters over the wave, one atomic each (wave-uniform call).
+__device__ __forceinline__ void flush_work(WalkTotals* tot, uint32_t nblocks, uint32_t nsteps) {
+  unsigned long long b = nblocks, s = nsteps;
+  for (int m = 32; m > 0; m >>= 1) {
+    b += __shfl_xor(b, m, 64);
+    s += __shfl_xor(s, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&tot->blocks, b);
+    atomicAdd(&tot->steps, s);
+  }
+}
+
 // kBuckets = false: M[k] counts the meeting pairs of node k.
 // kBuckets = true (shared samples of a source block): a meeting pair r of node k
 // is counted in bucket j = #{b : T[k][b] <= r} of M[k * B + j], where T[k] holds
 // the block's per-source sample counts R_b(k) in ascending order; source b then
 // owns the meetings of buckets j <= #{b' : R_b'(k) < R_b(k)}, i.e. exactly the
 // meetings among its own pairs r < R_b(k).
+// Eight waves per SIMD (at most 64 VGPRs) measured faster than the looser
+// register budget the compiler picks by itself, despite a few spills.
 template <bool kBuckets>
-__global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
+__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void walk_pairs_kernel(
+    WalkArgs a) {
   const int lane = threadIdx.x & 63;
   const uint64_t total = a.tot->total;
   const int32_t nact = a.tot->n_active;
+  // samples per lane per chunk: long runs shorten the idle tail at the end of a
+  // chunk, bounded so that every wave still takes several chunks
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  uint64_t run = total / (waves * 64ull * 4ull);
+  run = run < kWalkMinRun ? kWalkMinRun : (run > kWalkMaxRun ? kWalkMaxRun : run);
+  const unsigned long long chunk = 64ull * run;
   // meeting count held for node cnt_node, flushed when the lane moves on
   int32_t cnt_node = -1;
   unsigned long long cnt = 0;
   int32_t cnt_bucket = 0;      // buckets only
   uint64_t next_thr = 0;       // buckets only: first threshold above the cached bucket
-  unsigned long long nblocks = 0, nsteps = 0;  // work counters for the roofline
+  uint32_t nblocks = 0, nsteps = 0;  // work counters for the roofline, flushed per chunk
+  // lifetimes of the four pairs 4q..4q+3 of count index lk, 16 bits each (T <= 4096)
+  int32_t lk = -1;
+  uint64_t lq = 0, lt = 0;
+  auto lifetime = [&](uint64_t u) -> uint64_t {
+    uint64_t T = 0;
+#pragma unroll
+    for (int q = 1; q <= kLifeRegs; ++q) T += u < a.thr[q] ? 1 : 0;  // thresholds decrease
+    if (T == kLifeRegs)
+      while ((int32_t)T < a.tmax && u < a.thr[T + 1]) ++T;
+    return T;
+  };
   for (;;) {
     unsigned long long c0 = 0;
-    if (lane == 0) c0 = atomicAdd(&a.tot->cursor, (unsigned long long)kWalkChunk);
+    if (lane == 0) c0 = atomicAdd(&a.tot->cursor, chunk);
     c0 = __shfl(c0, 0, 64);
     if (c0 >= total) break;
     // this lane's run of samples [i, iend)
-    uint64_t i = c0 + (uint64_t)lane * kWalkPerLane;
-    const uint64_t iend = (i + kWalkPerLane < total) ? i + kWalkPerLane : total;
+    uint64_t i = c0 + (uint64_t)lane * run;
+    const uint64_t iend = (i + run < total) ? i + run : total;
     int32_t p = 0;
     uint64_t pbeg = 0, pend = 0;
+    // ids of the node of slot p: count index, first sample, graph id, stream id
+    int32_t pk = 0;
+    uint64_t prb = 0;
+    auto load_node = [&]() {
+      pk = a.active[p];
+      prb = a.r_begin ? a.r_begin[pk] : 0ull;
+    };
     if (i < iend) {
       // last active slot whose prefix is <= i
       int32_t lo = 0, hi = nact;  // prefix[lo] <= i < prefix[hi]
@@ -341,60 +384,73 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
       p = lo;
       pbeg = a.prefix[p];
       pend = a.prefix[p + 1];
+      load_node();
     }
     bool in_pair = false;
     int32_t k = 0, x = 0, y = 0, t = 0, T = 0, kg = 0;
     uint64_t r = 0, kc = 0;
     for (;;) {
-      const bool start = !in_pair && i < iend;
-      const bool busy = in_pair || start;
+      // out of a pair: start the next one; pairs whose cached lifetime is 0
+      // end at once, a pair without a cached lifetime needs its lifetime block
+      bool need_life = false;
+      if (!in_pair) {
+        while (i < iend) {
+          if (i >= pend) {
+            do {
+              ++p;
+              pbeg = pend;
+              pend = a.prefix[p + 1];
+            } while (i >= pend);
+            load_node();
+          }
+          const uint64_t rr = prb + (i - pbeg);
+          if (pk == lk && (rr >> 2) == lq) {
+            const int32_t TT = (int32_t)((lt >> (16 * (rr & 3))) & 0xffffu);
+            ++i;
+            if (TT == 0) continue;  // both walks stop at once: no meeting
+            k = pk;
+            r = rr;
+            T = TT;
+            kg = a.to_graph ? a.to_graph[k] : k;
+            kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
+            x = kg;
+            y = kg;
+            t = 0;
+            in_pair = true;
+            break;
+          }
+          k = pk;
+          r = rr;
+          kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
+          need_life = true;
+          break;
+        }
+      }
+      const bool busy = in_pair || need_life;
       if (!__any(busy)) break;
       if (!busy) continue;
-      uint64_t blk;
-      if (start) {
-        while (i >= pend) {
-          ++p;
-          pbeg = pend;
-          pend = a.prefix[p + 1];
-        }
-        k = a.active[p];
-        r = (a.r_begin ? a.r_begin[k] : 0ull) + (i - pbeg);
-        kg = a.to_graph ? a.to_graph[k] : k;
-        kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
-        ++i;
-        blk = 0;
-      } else {
-        blk = (uint64_t)((t + 1) >> 1);
-      }
-      const Words w = philox4x64_10(kc, r, blk, 0ull, a.seed, 0ull);
+      // one Philox block per lane and iteration: a lifetime block (k, q, 0, 1)
+      // or the movement block (k, r, j, 0) of steps 2j+1 and 2j+2
+      const uint64_t c1 = need_life ? (r >> 2) : r;
+      const uint64_t c2 = need_life ? 0ull : (uint64_t)(t >> 1);
+      const uint64_t c3 = need_life ? 1ull : 0ull;
+      const Words w = philox4x64_10(kc, c1, c2, c3, a.seed, 0ull);
       ++nblocks;
-      int res = 0;  // 0: go on, 1: met, -1: ended without meeting
-      if (start) {
-        T = 0;
-        while (T < a.tmax && w.w0 < a.thr[T + 1]) ++T;
-        x = kg;
-        y = kg;
-        t = 0;
-        in_pair = true;
-        if (T == 0) {
-          res = -1;
-        } else {
-          const int st = walk_step(a.in_off, a.in_idx, x, y, w.w1, w.w2);
-          ++nsteps;
-          t = 1;
-          res = st != 0 ? st : (t == T ? -1 : 0);
-        }
-      } else {
-        int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
+      if (need_life) {
+        lk = k;
+        lq = r >> 2;
+        lt = lifetime(w.w0) | (lifetime(w.w1) << 16) | (lifetime(w.w2) << 32) | (lifetime(w.w3) << 48);
+        continue;  // the pair starts from the cache on the next iteration
+      }
+      int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
+      t += 1;
+      ++nsteps;
+      if (st == 0 && t < T) {
+        st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
         t += 1;
         ++nsteps;
-        if (st == 0 && t < T) {
-          st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
-          t += 1;
-          ++nsteps;
-        }
-        res = st != 0 ? st : (t >= T ? -1 : 0);
       }
+      const int res = st != 0 ? st : (t >= T ? -1 : 0);  // 1: met, -1: ended, 0: go on
       if (res != 0) {
         in_pair = false;
         if (res > 0) {
@@ -433,20 +489,14 @@ __global__ __launch_bounds__(kWalkThreads) void walk_pairs_kernel(WalkArgs a) {
         }
       }
     }
+    // every lane leaves the pair loop together: flush the 32-bit work counters per chunk
+    flush_work(a.tot, nblocks, nsteps);
+    nblocks = nsteps = 0;
   }
   if (cnt) {
     if constexpr (kBuckets) atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], cnt);
     else atomicAdd(&a.M[cnt_node], cnt);
     atomicAdd(&a.tot->meets, cnt);
-  }
-  // one atomic per wave for the work counters
-  for (int m = 32; m > 0; m >>= 1) {
-    nblocks += __shfl_xor(nblocks, m, 64);
-    nsteps += __shfl_xor(nsteps, m, 64);
-  }
-  if (lane == 0) {
-    atomicAdd(&a.tot->blocks, nblocks);
-    atomicAdd(&a.tot->steps, nsteps);
   }
 }
 
