@@ -366,14 +366,14 @@ void free_batch_plans(es_ctx* ctx) {
   BatchPlan* p = ctx->plans;
   while (p) {
     BatchPlan* nx = p->next;
-    hipFree(p->ents);
-    hipFree(p->tiles_fwd);
-    hipFree(p->tiles_back);
-    hipFree(p->long_fwd);
-    hipFree(p->long_back);
-    hipFree(p->src_int);
-    hipFree(p->outs);
-    if (p->exec) hipGraphExecDestroy(p->exec);
+    (void)hipFree(p->ents);
+    (void)hipFree(p->tiles_fwd);
+    (void)hipFree(p->tiles_back);
+    (void)hipFree(p->long_fwd);
+    (void)hipFree(p->long_back);
+    (void)hipFree(p->src_int);
+    (void)hipFree(p->outs);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
     delete p;
     p = nx;
   }
@@ -644,14 +644,15 @@ es_status autotune(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opt
         // sources: the B highest-degree nodes (internal ids 0..B-1)
         std::vector<int32_t> src(B);
         for (int32_t b = 0; b < B; ++b) src[b] = std::min(b, g->n - 1);
-        hipMemcpy(p.src_int, src.data(), 4 * B, hipMemcpyHostToDevice);
+        const hipError_t ec = hipMemcpy(p.src_int, src.data(), 4 * B, hipMemcpyHostToDevice);
+        if (ec != hipSuccess) st = hip_fail(ctx, ec, "hipMemcpy(tuning sources)");
         const double sc = std::sqrt(o->c);
         dim3 egrid(p.max_nb_blocks, 1);
         bat_forward_init<<<egrid, 256, 0, ctx->stream>>>(p.ents, p.src_int, 1.0 - sc, bb.levels, bb.q[0]);
         const int spmm_f = ceil_div(p.ntf, kSpmmThreads / 64);
         float tot = 0;
-        for (int rep = 0; rep < 2; ++rep) {
-          hipEventRecord(e0, ctx->stream);
+        for (int rep = 0; rep < 2 && st == ES_OK; ++rep) {
+          (void)hipEventRecord(e0, ctx->stream);
           for (int32_t l = 1; l <= p.L; ++l) {
             FwdOp op{bb.q[(l - 1) & 1], bb.q[l & 1], bb.levels + (int64_t)l * p.NB, bb.acc, sc};
             if (p.ntf) spmm_kernel<FwdOp><<<spmm_f, kSpmmThreads, 0, ctx->stream>>>(p.tiles_fwd, p.ntf, p.ents, op);
@@ -659,25 +660,26 @@ es_status autotune(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opt
               long_finish_kernel<FwdOp><<<ceil_div((int64_t)p.nlf * kBatchMaxB, 256), 256, 0, ctx->stream>>>(
                   p.long_fwd, p.nlf, p.ents, op);
           }
-          hipEventRecord(e1, ctx->stream);
-          hipEventSynchronize(e1);
+          (void)hipEventRecord(e1, ctx->stream);
+          const hipError_t es = hipEventSynchronize(e1);
+          if (es != hipSuccess) st = hip_fail(ctx, es, "tuning launch");
           float ms = 0;
-          hipEventElapsedTime(&ms, e0, e1);
+          (void)hipEventElapsedTime(&ms, e0, e1);
           if (rep == 1) tot = ms;
         }
-        if (tot < best) {
+        if (st == ES_OK && tot < best) {
           best = tot;
           *bestW = W;
           *bestG = G;
         }
       }
-      hipFree(p.ents);
-      hipFree(p.tiles_fwd);
-      hipFree(p.tiles_back);
-      hipFree(p.long_fwd);
-      hipFree(p.long_back);
-      hipFree(p.src_int);
-      hipFree(p.outs);
+      (void)hipFree(p.ents);
+      (void)hipFree(p.tiles_fwd);
+      (void)hipFree(p.tiles_back);
+      (void)hipFree(p.long_fwd);
+      (void)hipFree(p.long_back);
+      (void)hipFree(p.src_int);
+      (void)hipFree(p.outs);
       ES_TRY(st);
     }
   }
@@ -796,7 +798,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
     int count = 0;
     for (BatchPlan* q = ctx->plans; q; q = q->next)
       if (++count >= 8 && q->next) {
-        hipStreamSynchronize(ctx->stream);  // an evicted graph may still be running
+        (void)hipStreamSynchronize(ctx->stream);  // an evicted graph may still be running
         BatchPlan* rest = q->next;
         q->next = nullptr;
         BatchPlan* saved = ctx->plans;
@@ -823,7 +825,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   }
   std::vector<void*> ws_now(ctx->ws.begin(), ctx->ws.end());
   if (plan->exec && plan->ws != ws_now) {
-    hipGraphExecDestroy(plan->exec);
+    (void)hipGraphExecDestroy(plan->exec);
     plan->exec = nullptr;
   }
   // per-call inputs: sources (internal ids) and output pointers, in block order
@@ -857,7 +859,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
       ES_TRY(st);
       if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamEndCapture");
       const hipError_t ei = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       if (ei != hipSuccess) return hip_fail(ctx, ei, "hipGraphInstantiate");
       plan->ws = ws_now;
     }

@@ -37,8 +37,8 @@ void* workspace(es_ctx* ctx, int slot, size_t bytes, es_status* st) {
   if (ctx->ws_bytes[slot] < bytes) {
     if (ctx->ws[slot]) {
       // the stream may still use the old buffer
-      hipStreamSynchronize(ctx->stream);
-      hipFree(ctx->ws[slot]);
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(ctx->ws[slot]);
       ctx->ws[slot] = nullptr;
       ctx->ws_bytes[slot] = 0;
     }
@@ -152,11 +152,11 @@ es_status build_plan(es_ctx* ctx, const int32_t* off, int32_t n, SpmvPlan* plan)
 }
 
 void free_plan(SpmvPlan* plan) {
-  hipFree(plan->blocks);
-  hipFree(plan->long_p0);
-  hipFree(plan->long_nch);
-  hipFree(plan->counters);
-  hipFree(plan->partials);
+  (void)hipFree(plan->blocks);
+  (void)hipFree(plan->long_p0);
+  (void)hipFree(plan->long_nch);
+  (void)hipFree(plan->counters);
+  (void)hipFree(plan->partials);
   *plan = SpmvPlan{};
 }
 
@@ -270,15 +270,15 @@ es_status es_ctx_create(int device, void* hip_stream, es_ctx** out) {
 
 es_status es_ctx_destroy(es_ctx* ctx) {
   if (!ctx) return ES_EINVAL;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   es::free_batch_plans(ctx);
-  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
-  for (void* p : ctx->ws) hipFree(p);
-  hipFree(ctx->thr);
-  hipFree(ctx->mlp_w);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  for (void* p : ctx->ws) (void)hipFree(p);
+  (void)hipFree(ctx->thr);
+  (void)hipFree(ctx->mlp_w);
   for (auto& e : ctx->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return ES_OK;
 }
@@ -374,18 +374,18 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
 
 es_status es_graph_destroy(es_graph* g) {
   if (!g) return ES_EINVAL;
-  hipSetDevice(g->device);
-  hipDeviceSynchronize();
-  hipFree(g->out_off);
-  hipFree(g->out_idx);
-  hipFree(g->in_off);
-  hipFree(g->in_idx);
-  hipFree(g->inv_din);
-  hipFree(g->din_int);
-  hipFree(g->din_ext);
-  hipFree(g->dout_ext);
-  hipFree(g->ext_of);
-  hipFree(g->int_of);
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(g->out_off);
+  (void)hipFree(g->out_idx);
+  (void)hipFree(g->in_off);
+  (void)hipFree(g->in_idx);
+  (void)hipFree(g->inv_din);
+  (void)hipFree(g->din_int);
+  (void)hipFree(g->din_ext);
+  (void)hipFree(g->dout_ext);
+  (void)hipFree(g->ext_of);
+  (void)hipFree(g->int_of);
   free_plan(&g->fwd);
   free_plan(&g->back);
   delete g;

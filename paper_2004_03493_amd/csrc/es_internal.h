@@ -22,8 +22,8 @@ namespace es {
 //    chunks of kLongChunk entries, one workgroup per chunk, whose partial
 //    sums are combined in chunk order by the last chunk to finish.
 // ---------------------------------------------------------------------------
-constexpr int kSpmvThreads = 256;
-constexpr int kSpmvNnz = 2048;
+constexpr int kSpmvThreads = 512;
+constexpr int kSpmvNnz = 8192;
 constexpr int kSpmvRows = 512;
 constexpr int kLongChunk = 8192;
 

@@ -58,15 +58,21 @@ struct FwdGather {
   __device__ __forceinline__ int64_t operator()(int32_t j) const { return q[j]; }
 };
 
+// Epilogues split into the per-row operands (loaded early, with the column
+// ids, so their latency overlaps the gathers) and the arithmetic.
 struct FwdEpi {
+  struct Row {
+    double inv_din;
+  };
   double sc;
   const double* __restrict__ inv_din;
   double* __restrict__ pi_l;
   int64_t* __restrict__ q_next;
-  __device__ __forceinline__ void operator()(int32_t r, int64_t acc) const {
+  __device__ __forceinline__ Row load(int32_t r) const { return Row{inv_din[r]}; }
+  __device__ __forceinline__ void apply(int32_t r, int64_t acc, const Row& d) const {
     const double p = sc * ((double)acc * kFixInv);
     pi_l[r] = p;
-    q_next[r] = (int64_t)rint((p * inv_din[r]) * kFix);
+    q_next[r] = (int64_t)rint((p * d.inv_din) * kFix);
   }
 };
 
@@ -76,13 +82,17 @@ struct BackGather {
 };
 
 struct BackEpi {
+  struct Row {
+    double inv_din, D, pil;
+  };
   double sc, a;
   const double* __restrict__ inv_din;
   const double* __restrict__ D;
   const double* __restrict__ pil;
   double* __restrict__ s_next;
-  __device__ __forceinline__ void operator()(int32_t r, double acc) const {
-    s_next[r] = sc * (inv_din[r] * acc) + a * (D[r] * pil[r]);
+  __device__ __forceinline__ Row load(int32_t r) const { return Row{inv_din[r], D[r], pil[r]}; }
+  __device__ __forceinline__ void apply(int32_t r, double acc, const Row& d) const {
+    s_next[r] = sc * (d.inv_din * acc) + a * (d.D * d.pil);
   }
 };
 
@@ -94,19 +104,34 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
                                                                  const int32_t* __restrict__ long_p0,
                                                                  const int32_t* __restrict__ long_nch,
                                                                  uint32_t* __restrict__ counters) {
+  using Row = typename Epi::Row;
   __shared__ V vals[kSpmvNnz];
+  __shared__ int32_t roff[kSpmvRows + 1];
+  __shared__ Row rdat[kSpmvRows];
   __shared__ V red[kSpmvThreads / 64];
   const BlockDesc b = blocks[blockIdx.x];
   const int tid = threadIdx.x;
   if (b.row1 >= 0) {
     const int nnz = b.e1 - b.e0;
+    const int nrows = b.row1 - b.row0;
     constexpr int kPer = kSpmvNnz / kSpmvThreads;
+    constexpr int kRowsPer = (kSpmvRows + 1 + kSpmvThreads - 1) / kSpmvThreads;  // rows + 1 offsets
+    // 1. everything that depends only on the block: column ids, row offsets, row operands
+    int32_t col[kPer];
     if (nnz > 0) {
       // branch-free so that all kPer index loads, then all kPer gathers, are in flight at once;
       // lanes past the end re-read the block's last entry and do not store it
-      int32_t col[kPer];
 #pragma unroll
       for (int t = 0; t < kPer; ++t) col[t] = idx[b.e0 + min(t * kSpmvThreads + tid, nnz - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kRowsPer; ++t) {
+      const int rr = t * kSpmvThreads + tid;
+      if (rr < nrows) rdat[rr] = epi.load(b.row0 + rr);
+      if (rr <= nrows) roff[rr] = off[b.row0 + rr] - b.e0;
+    }
+    // 2. the gathers
+    if (nnz > 0) {
       V v[kPer];
 #pragma unroll
       for (int t = 0; t < kPer; ++t) v[t] = gather(col[t]);
@@ -117,20 +142,18 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
       }
     }
     __syncthreads();
-    const int nrows = b.row1 - b.row0;
-    // lanes per row: the largest power of two <= threads / rows, at most 64
+    // 3. rows from LDS: lanes per row = the largest power of two <= threads / rows, at most 64
     int g = 1;
     while (g < 64 && g * 2 * nrows <= kSpmvThreads) g *= 2;
     const int lane_in_g = tid & (g - 1);
     const int groups = kSpmvThreads / g;
     // all lanes of a group share rr, so a group's shuffles run with the whole group active
     for (int rr = tid / g; rr < nrows; rr += groups) {
-      const int r = b.row0 + rr;
-      const int s = off[r] - b.e0, e = off[r + 1] - b.e0;
+      const int s0 = roff[rr], e = roff[rr + 1];
       V acc = 0;
-      for (int k = s + lane_in_g; k < e; k += g) acc += vals[k];
+      for (int k = s0 + lane_in_g; k < e; k += g) acc += vals[k];
       if (g > 1) acc = group_sum(acc, g);
-      if (lane_in_g == 0) epi(r, acc);
+      if (lane_in_g == 0) epi.apply(b.row0 + rr, acc, rdat[rr]);
     }
   } else {
     const int lid = -b.row1 - 1;
@@ -159,7 +182,7 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
         V tot = 0;
         for (int c = 0; c < nch; ++c) tot += load_partial(&partials[p0 + c]);
         __hip_atomic_store(&counters[lid], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        epi(r, tot);
+        epi.apply(r, tot, epi.load(r));
       }
     }
   }
