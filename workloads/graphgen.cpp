@@ -10,8 +10,8 @@
 //
 // Candidate edges are drawn from a counter-based hash (splitmix64 finaliser
 // over (seed, candidate index, draw index)), so candidate i is the same no
-// matter which thread makes it.  Distinct edges are kept in order of first
-// appearance in the candidate sequence until m of them exist.
+// matter which thread makes it.  The edge set is the first m distinct edges
+// in order of first appearance in the candidate sequence.
 
 #include <algorithm>
 #include <cmath>
@@ -43,60 +43,137 @@ struct KeyIdx {
   uint64_t idx;
 };
 
-// Shared driver: `cand(i)` returns the packed key (src << 32 | dst) of
-// candidate i, or kInvalid when the candidate is rejected (self-loop, id
-// out of range).  Fills keys_out (sorted, unique) with exactly m keys.
-template <class Cand>
-int collect_unique(int64_t m, Cand cand, std::vector<uint64_t>& keys_out) {
+// Shared driver.  `cand(i)` returns the packed key (src << 32 | dst) of
+// candidate i before relabelling, or kInvalid when the candidate is rejected
+// (self-loop, id out of range); `relabel(key)` maps a key to its final ids
+// by a bijection.  Fills keys_out with the relabelled first m distinct keys
+// in order of first appearance among candidates 0, 1, 2, ..., sorted.
+//
+// The raw keys of candidates 0..N-1 are generated once into one array.
+// Distinctness is decided before relabelling (a bijection keeps it): valid
+// candidates are spread over buckets by a hash of the key (equal keys share
+// a bucket), each bucket sorted and reduced to its distinct keys with their
+// first candidate index, and the m distinct keys of smallest first index are
+// kept.  The result does not depend on N once N holds m distinct keys, so
+// when it does not, the array is extended and the dedup redone.
+template <class Cand, class Relabel>
+int collect_unique(int64_t m, Cand cand, Relabel relabel, std::vector<uint64_t>& keys_out) {
   keys_out.clear();
-  uint64_t next = 0;
-  int stalls = 0;
-  const uint64_t kMaxBatch = 1ull << 27;
-  while ((int64_t)keys_out.size() < m) {
-    uint64_t need = (uint64_t)(m - (int64_t)keys_out.size());
-    uint64_t batch = std::min<uint64_t>(kMaxBatch, std::max<uint64_t>(need + need / 4, 1u << 16));
-    std::vector<KeyIdx> c(batch);
-#pragma omp parallel for schedule(static)
-    for (int64_t t = 0; t < (int64_t)batch; ++t) {
-      uint64_t i = next + (uint64_t)t;
-      c[t] = KeyIdx{cand(i), i};
+  if (m == 0) return 0;
+  const int nthreads = omp_get_max_threads();
+  const int kBucketBits = 14;
+  const uint64_t nbuckets = 1ull << kBucketBits;
+  auto bucket_of = [](uint64_t key) -> uint64_t { return mix64(key) >> (64 - kBucketBits); };
+  std::vector<uint64_t> raw;
+  uint64_t N = (uint64_t)m + (uint64_t)m / 4 + 1024;
+  for (int attempt = 0; attempt < 40; ++attempt) {
+    // raw keys of candidates [raw.size(), N)
+    const uint64_t N0 = raw.size();
+    raw.resize(N);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int64_t i = (int64_t)N0; i < (int64_t)N; ++i) raw[i] = cand((uint64_t)i);
+    // counts per (thread, bucket) over contiguous ranges of candidates
+    std::vector<uint64_t> counts((size_t)nthreads * nbuckets, 0);
+#pragma omp parallel num_threads(nthreads)
+    {
+      const int t = omp_get_thread_num();
+      const uint64_t lo = N * t / nthreads, hi = N * (t + 1) / nthreads;
+      uint64_t* c = counts.data() + (size_t)t * nbuckets;
+      for (uint64_t i = lo; i < hi; ++i)
+        if (raw[i] != kInvalid) c[bucket_of(raw[i])]++;
     }
-    next += batch;
-    // drop rejected candidates
-    c.erase(std::remove_if(c.begin(), c.end(), [](const KeyIdx& a) { return a.key == kInvalid; }),
-            c.end());
-    // unique by key, keeping the first appearance
-    __gnu_parallel::sort(c.begin(), c.end(), [](const KeyIdx& a, const KeyIdx& b) {
-      return a.key < b.key || (a.key == b.key && a.idx < b.idx);
-    });
-    c.erase(std::unique(c.begin(), c.end(), [](const KeyIdx& a, const KeyIdx& b) { return a.key == b.key; }),
-            c.end());
-    // drop keys already kept
-    std::vector<char> fresh(c.size());
-#pragma omp parallel for schedule(static)
-    for (int64_t t = 0; t < (int64_t)c.size(); ++t)
-      fresh[t] = !std::binary_search(keys_out.begin(), keys_out.end(), c[t].key);
-    size_t w = 0;
-    for (size_t t = 0; t < c.size(); ++t)
-      if (fresh[t]) c[w++] = c[t];
-    c.resize(w);
-    if (c.empty()) {
-      if (++stalls > 64) return -1;
+    std::vector<uint64_t> off((size_t)nthreads * nbuckets, 0), bstart(nbuckets + 1, 0);
+    uint64_t acc = 0;
+    for (uint64_t b = 0; b < nbuckets; ++b) {
+      bstart[b] = acc;
+      for (int t = 0; t < nthreads; ++t) {
+        off[(size_t)t * nbuckets + b] = acc;
+        acc += counts[(size_t)t * nbuckets + b];
+      }
+    }
+    bstart[nbuckets] = acc;
+    std::vector<uint64_t>().swap(counts);
+    std::vector<KeyIdx> cands(acc);
+#pragma omp parallel num_threads(nthreads)
+    {
+      const int t = omp_get_thread_num();
+      const uint64_t lo = N * t / nthreads, hi = N * (t + 1) / nthreads;
+      uint64_t* o = off.data() + (size_t)t * nbuckets;
+      for (uint64_t i = lo; i < hi; ++i)
+        if (raw[i] != kInvalid) cands[o[bucket_of(raw[i])]++] = KeyIdx{raw[i], i};
+    }
+    // per bucket: sort by (key, index), keep each key's first appearance
+    std::vector<uint64_t> ucount(nbuckets, 0);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t b = 0; b < (int64_t)nbuckets; ++b) {
+      KeyIdx* first = cands.data() + bstart[b];
+      KeyIdx* last = cands.data() + bstart[b + 1];
+      std::sort(first, last, [](const KeyIdx& x, const KeyIdx& y) {
+        return x.key < y.key || (x.key == y.key && x.idx < y.idx);
+      });
+      KeyIdx* e = std::unique(first, last, [](const KeyIdx& x, const KeyIdx& y) { return x.key == y.key; });
+      ucount[b] = (uint64_t)(e - first);
+    }
+    uint64_t U = 0;
+    for (uint64_t c : ucount) U += c;
+    if (U < (uint64_t)m) {
+      // not enough distinct keys yet: more candidates, sized from this yield
+      const double grow = 1.15 * (double)m / (double)std::max<uint64_t>(U, 1);
+      N = std::max(N + N / 8, (uint64_t)((double)N * std::min(grow, 8.0)));
       continue;
     }
-    stalls = 0;
-    // take new keys in candidate order
-    __gnu_parallel::sort(c.begin(), c.end(), [](const KeyIdx& a, const KeyIdx& b) { return a.idx < b.idx; });
-    if (c.size() > need) c.resize(need);
-    std::vector<uint64_t> add(c.size());
-    for (size_t t = 0; t < c.size(); ++t) add[t] = c[t].key;
-    std::vector<KeyIdx>().swap(c);
-    __gnu_parallel::sort(add.begin(), add.end());
-    std::vector<uint64_t> merged(keys_out.size() + add.size());
-    std::merge(keys_out.begin(), keys_out.end(), add.begin(), add.end(), merged.begin());
-    keys_out.swap(merged);
+    std::vector<uint64_t>().swap(raw);
+    // theta = the m-th smallest first-appearance index: histogram of the
+    // indices in 2^20 bins, then an exact selection inside the bin holding it
+    const int kBinBits = 20;
+    const uint64_t nbins = 1ull << kBinBits;
+    const uint64_t binw = (N + nbins - 1) / nbins;
+    std::vector<uint64_t> hist(nbins, 0);
+#pragma omp parallel num_threads(nthreads)
+    {
+      std::vector<uint64_t> h(nbins, 0);
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t b = 0; b < (int64_t)nbuckets; ++b)
+        for (uint64_t j = 0; j < ucount[b]; ++j) h[cands[bstart[b] + j].idx / binw]++;
+#pragma omp critical
+      for (uint64_t k = 0; k < nbins; ++k) hist[k] += h[k];
+    }
+    uint64_t below = 0, bin = 0;
+    while (below + hist[bin] < (uint64_t)m) below += hist[bin++];
+    std::vector<uint64_t> inbin;
+    inbin.reserve(hist[bin]);
+    for (uint64_t b = 0; b < nbuckets; ++b)
+      for (uint64_t j = 0; j < ucount[b]; ++j) {
+        const uint64_t idx = cands[bstart[b] + j].idx;
+        if (idx / binw == bin) inbin.push_back(idx);
+      }
+    const uint64_t rank = (uint64_t)m - below - 1;
+    std::nth_element(inbin.begin(), inbin.begin() + rank, inbin.end());
+    const uint64_t theta = inbin[rank];
+    // relabelled keys of every distinct key first seen at index <= theta
+    std::vector<uint64_t> keep(nbuckets + 1, 0);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+    for (int64_t b = 0; b < (int64_t)nbuckets; ++b) {
+      uint64_t k = 0;
+      for (uint64_t j = 0; j < ucount[b]; ++j) k += cands[bstart[b] + j].idx <= theta;
+      keep[b + 1] = k;
+    }
+    for (uint64_t b = 0; b < nbuckets; ++b) keep[b + 1] += keep[b];
+    if (keep[nbuckets] != (uint64_t)m) return -1;
+    keys_out.resize((size_t)m);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+    for (int64_t b = 0; b < (int64_t)nbuckets; ++b) {
+      uint64_t w = keep[b];
+      for (uint64_t j = 0; j < ucount[b]; ++j) {
+        const KeyIdx& ki = cands[bstart[b] + j];
+        if (ki.idx <= theta) keys_out[w++] = relabel(ki.key);
+      }
+    }
+    std::vector<KeyIdx>().swap(cands);
+    __gnu_parallel::sort(keys_out.begin(), keys_out.end());
+    return 0;
   }
-  return 0;
+  return -1;
 }
 
 void unpack(const std::vector<uint64_t>& keys, int32_t* src, int32_t* dst) {
@@ -152,19 +229,21 @@ int gg_rmat(int32_t n, int64_t m, double a, double b, double c, double d, uint64
       } else {
         u = h >> 32;
       }
-      uint64_t sb, tb;
-      if (u < ta) { sb = 0; tb = 0; }
-      else if (u < tab) { sb = 0; tb = 1; }
-      else if (u < tabc) { sb = 1; tb = 0; }
-      else { sb = 1; tb = 1; }
+      // quadrant: [0, ta) -> (0,0), [ta, tab) -> (0,1), [tab, tabc) -> (1,0),
+      // [tabc, 2^32) -> (1,1); branch-free, the draws are unpredictable
+      const uint64_t sb = (uint64_t)(u >= tab);
+      const uint64_t tb = (uint64_t)(u >= ta) ^ (uint64_t)(u >= tab) ^ (uint64_t)(u >= tabc);
       s = (s << 1) | sb;
       t = (t << 1) | tb;
     }
     if (s >= (uint64_t)n || t >= (uint64_t)n || s == t) return kInvalid;
-    return ((uint64_t)(uint32_t)perm[s] << 32) | (uint64_t)(uint32_t)perm[t];
+    return (s << 32) | t;
+  };
+  auto relabel = [&](uint64_t key) -> uint64_t {
+    return ((uint64_t)(uint32_t)perm[key >> 32] << 32) | (uint64_t)(uint32_t)perm[key & 0xffffffffu];
   };
   std::vector<uint64_t> keys;
-  if (collect_unique(m, cand, keys) != 0) return -1;
+  if (collect_unique(m, cand, relabel, keys) != 0) return -1;
   unpack(keys, src, dst);
   return 0;
 }
@@ -196,7 +275,7 @@ int gg_chung_lu(int32_t n, int64_t m, double gamma, uint64_t seed, int32_t* src,
     return (s << 32) | t;
   };
   std::vector<uint64_t> keys;
-  if (collect_unique(m, cand, keys) != 0) return -1;
+  if (collect_unique(m, cand, [](uint64_t key) { return key; }, keys) != 0) return -1;
   unpack(keys, src, dst);
   return 0;
 }
