@@ -98,6 +98,26 @@ def features(g, pi: np.ndarray, c: float) -> np.ndarray:
     return F
 
 
+def features_at(g, pi: np.ndarray, c: float, nodes) -> np.ndarray:
+    """The rows of `features` for the given nodes only, one node at a time
+    (for graphs too large to form every row on the CPU)."""
+    nodes = np.asarray(nodes, dtype=np.int64)
+    p2 = pi * pi
+    tot = p2.sum()
+    F = np.zeros((len(nodes), NF))
+    for r, k in enumerate(nodes):
+        d = int(g.din[k])
+        nb = g.in_idx[g.in_off[k]:g.in_off[k + 1]]
+        nb_din = g.din[nb].astype(np.float64)
+        F[r, 0] = math.log1p(d)
+        F[r, 1] = math.log1p(float(g.dout[k]))
+        F[r, 2] = math.log1p(nb_din.sum() / d) if d > 0 else 0.0
+        F[r, 3] = math.log1p(nb_din.max()) if d > 0 else 0.0
+        F[r, 4] = math.log1p(g.n * p2[k] / tot) if tot > 0 else 0.0
+        F[r, 5] = c / d if d > 0 else 0.0
+    return F
+
+
 def forward(theta, X, c):
     """Return (p, cache) for inputs X [N][6]."""
     W1, b1, W2, b2, w3, b3 = unpack(theta)
