@@ -53,9 +53,12 @@ def parse():
     p.add_argument("--cpu-sample-pairs", type=float, default=2e8)
     p.add_argument("--copy-calibration", action="store_true",
                    help="after the timed region, copy 1 GiB once (reference dispatch for HBM counters)")
-    p.add_argument("--workload", default="single", choices=["single", "batch64", "uneven"],
+    p.add_argument("--workload", default="single", choices=["single", "batch64", "uneven", "rmat42m"],
                    help="single: the R-MAT 2^20 single-source line; batch64 / uneven: batched queries "
-                        "against single-source queries on the same GPU")
+                        "against single-source queries on the same GPU; rmat42m: R-MAT n=4.2e7, m=1.4e9 "
+                        "with the learned walk budget against the pi^2 rule")
+    p.add_argument("--ref-factor", type=float, default=16.0,
+                   help="rmat42m: budget multiple of the pi^2 reference run that errors are measured against")
     p.add_argument("--hip-graph", type=int, default=1)
     return p.parse_args()
 
@@ -204,11 +207,137 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_main(args):
+    """R-MAT n=4.2e7, m=1.4e9: the learned walk budget against the pi^2 rule.
+
+    The budget network is trained on the GPU from walk estimates on small
+    training graphs (none of them the evaluation graph).  Both allocations
+    are timed on the same sources at the same r_scale; their accuracy is
+    the MaxError against a pi^2 run with --ref-factor times the budget and
+    another walk seed, at equal total pairs."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2004_03493_amd import binding as es
+    from paper_2004_03493_amd import learned
+
+    wl = workloads.RMAT_42M
+    c, eps = wl.c, wl.eps
+    ctx = es.Context(0)
+    t0 = time.time()
+    Fs, Rs, Ms = [], [], []
+    specs = [("rmat", 1 << 16, 33 << 16, 601), ("rmat", 1 << 18, 33 << 18, 602), ("chung_lu", 1 << 16, 20 << 16, 603)]
+    for i, (kind, n, m, seed) in enumerate(specs):
+        s_, d_ = workloads.rmat(n, m, seed) if kind == "rmat" else workloads.chung_lu(n, m, seed)
+        gt = es.Graph(ctx, n, s_, d_)
+        ut = int(workloads.pick_sources(n, d_, 1, seed + 1)[0])
+        F, R, M = learned.collect(ctx, gt, ut, c, 1e-4, 4000, seed + 2)
+        Fs.append(F); Rs.append(R); Ms.append(M)
+        torch.cuda.synchronize()
+        gt.close()
+    F, R, M = torch.cat(Fs), torch.cat(Rs), torch.cat(Ms)
+    w, losses = learned.train(ctx, F, R, M, c, epochs=600, lr=3e-3, seed=7)
+    es.es_mlp_load(ctx, w)
+    del F, R, M, Fs, Rs, Ms
+    log(f"# network trained on {sum(x[1] for x in specs)} nodes in {time.time() - t0:.1f}s, "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    t0 = time.time()
+    src, dst = wl.graph()
+    sources = [int(x) for x in wl.sources(dst)]
+    log(f"# graph generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    g = es.Graph(ctx, wl.n, src, dst)
+    del src, dst
+    log(f"# graph on device in {time.time() - t0:.1f}s: n={g.n} m={g.m}")
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
+    val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
+
+    def query(u, alloc, seed, r_scale, out):
+        st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc), out)
+        es.es_topk(ctx, out, g.n, u, args.topk, idx, val)
+        return st
+
+    timed = {}
+    for name, alloc in (("pi2", es.ES_ALLOC_PI2), ("learned", es.ES_ALLOC_LEARNED)):
+        for i in range(args.warmup):
+            query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s)
+        torch.cuda.synchronize()
+        stats = []
+        t = time.perf_counter()
+        for i in range(args.steps):
+            stats.append(query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s))
+            torch.cuda.synchronize()
+            log(f"# {name} step {i}: pairs={stats[-1].pairs} walk {stats[-1].ms_walk:.1f} ms")
+        timed[name] = (time.perf_counter() - t, stats)
+    # accuracy at equal total pairs against a larger-budget pi^2 run
+    ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    acc = {"pi2": [], "learned": []}
+    pairs = {"pi2": 0, "learned": 0}
+    for u in sources[:2]:
+        query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
+        for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
+            for name, alloc in (("pi2", es.ES_ALLOC_PI2), ("learned", es.ES_ALLOC_LEARNED)):
+                st = query(u, alloc, seed, args.r_scale, s)
+                acc[name].append(float((s - ref).abs().max()))
+                pairs[name] += st.pairs
+        log(f"# accuracy u={u}: pi2 {acc['pi2'][-2:]} learned {acc['learned'][-2:]}")
+    L = timed["pi2"][1][0].L
+    fwd_bytes = L * (4.0 * g.m + 28.0 * g.n)
+    back_bytes = L * (4.0 * g.m + 44.0 * g.n)
+
+    def summary(name):
+        el, st = timed[name]
+        walk_s = sum(x.ms_walk for x in st) / 1e3
+        return {
+            "queries_per_s": len(st) / el,
+            "pairs_per_query_mean": float(np.mean([x.pairs for x in st])),
+            "walk_pairs_per_s": sum(x.pairs for x in st) / walk_s,
+            "ms_forward": float(np.mean([x.ms_forward for x in st])),
+            "ms_budget": float(np.mean([x.ms_budget for x in st])),
+            "ms_walk": float(np.mean([x.ms_walk for x in st])),
+            "ms_backward": float(np.mean([x.ms_backward for x in st])),
+        }
+
+    pl, pp = summary("learned"), summary("pi2")
+    el = timed["learned"][0]
+    out = {
+        "metric": "exact single-source SimRank queries/s at eps=1e-6 (learned walk budget)",
+        "value": args.steps / el,
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "n": g.n, "m": g.m, "c": c, "eps": eps, "L": L, "sources": sources,
+                   "r_scale": args.r_scale, "topk": args.topk, "alloc": "learned"},
+        "learned": pl,
+        "pi2": pp,
+        "roofline_spmv": {
+            "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
+            "achieved": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "backward_achieved": back_bytes / (pp["ms_backward"] / 1e3) / 1e9,
+        },
+        "accuracy": {
+            "reference": f"pi^2 allocation, {args.ref_factor:g}x the budget, walk seed {wl.seed_walk + 1000}",
+            "sources": sources[:2], "seeds": [wl.seed_walk + 1, wl.seed_walk + 2],
+            "max_error_pi2": acc["pi2"], "max_error_learned": acc["learned"],
+            "mean_ratio_pi2_over_learned": float(np.mean(acc["pi2"]) / np.mean(acc["learned"])),
+            "pairs_pi2": int(pairs["pi2"]), "pairs_learned": int(pairs["learned"]),
+        },
+        "projected_full_budget_s_per_query": float(pl["pairs_per_query_mean"] / args.r_scale / pl["walk_pairs_per_s"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "rmat42m":
+        return learned_main(args)
     if args.workload != "single":
         return batch_main(args)
     import numpy as np
