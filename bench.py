@@ -231,8 +231,7 @@ def learned_main(args):
     for i, (kind, n, m, seed) in enumerate(specs):
         s_, d_ = workloads.rmat(n, m, seed) if kind == "rmat" else workloads.chung_lu(n, m, seed)
         gt = es.Graph(ctx, n, s_, d_)
-        ut = int(workloads.pick_sources(n, d_, 1, seed + 1)[0])
-        F, R, M = learned.collect(ctx, gt, ut, c, 1e-4, 4000, seed + 2)
+        F, R, M = learned.collect(ctx, gt, c, 4000, seed + 2)
         Fs.append(F); Rs.append(R); Ms.append(M)
         torch.cuda.synchronize()
         gt.close()
@@ -275,7 +274,7 @@ def learned_main(args):
     ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
     acc = {"pi2": [], "learned": []}
     pairs = {"pi2": 0, "learned": 0}
-    for u in sources[:2]:
+    for u in sources[:4]:
         query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
         for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
             for name, alloc in (("pi2", es.ES_ALLOC_PI2), ("learned", es.ES_ALLOC_LEARNED)):
@@ -321,7 +320,8 @@ def learned_main(args):
         },
         "accuracy": {
             "reference": f"pi^2 allocation, {args.ref_factor:g}x the budget, walk seed {wl.seed_walk + 1000}",
-            "sources": sources[:2], "seeds": [wl.seed_walk + 1, wl.seed_walk + 2],
+            "sources": sources[:4], "seeds": [wl.seed_walk + 1, wl.seed_walk + 2],
+            "v_floor_ratio": es.ES_LEARNED_FLOOR,
             "max_error_pi2": acc["pi2"], "max_error_learned": acc["learned"],
             "mean_ratio_pi2_over_learned": float(np.mean(acc["pi2"]) / np.mean(acc["learned"])),
             "pairs_pi2": int(pairs["pi2"]), "pairs_learned": int(pairs["learned"]),

@@ -84,7 +84,11 @@ typedef struct {
   int32_t alloc;             /* es_alloc                                                    */
   int32_t exact_small_din;   /* nonzero: nodes with d_in 0 / 1 take D = 1 / 1-c, no samples  */
   const double* d_override;  /* device [n] or NULL: use this diagonal instead of sampling   */
+  double v_floor_ratio;      /* ES_ALLOC_LEARNED: floor f in [0, 1] on v(k) / vbar (below;
+                                ES_LEARNED_FLOOR = 1/2 recommended, 0 = none)              */
 } es_query_opts;
+
+#define ES_LEARNED_FLOOR 0.5
 
 typedef struct {
   int32_t L;                 /* number of levels                                    */
@@ -213,18 +217,29 @@ es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int3
  * The learned allocation keeps that factor: a network (6 -> 64 -> 64 -> 1,
  * ReLU, float32) predicts the meeting probability p(k) = 1 - D(k,k) in
  * (0, c) from local features, v(k) = max(p(1-p), 1e-6), and
- *   R(k) = ceil((R * (pi(k)*pi(k))) * (v(k) * S2/S1)),
- *   S1 = sum Q(pi^2 v), S2 = sum Q(pi^2), Q(x) = round(x * 2^62) (exact int64
- *   sums over the nodes that take samples),
+ *   vbar = S1/S2, w(k) = max(v(k), f vbar),
+ *   R(k) = ceil((R * (pi(k)*pi(k))) * (w(k) * S2/S3)),
+ *   S1 = sum Q(pi^2 v), S2 = sum Q(pi^2), S3 = sum Q(pi^2 w),
+ *   Q(x) = round(x * 2^62) (exact int64 sums over the nodes that take samples),
  * which keeps the pi^2 rule's total and gives every node with pi(k) > 0 at
- * least one pair, so D^ stays unbiased.  Weights: float32 [es_mlp_num_params()]
+ * least one pair, so D^ stays unbiased.  The floor f keeps every node at no
+ * less than about f times its pi^2 share: the bound behind Theorem 1
+ * (Bernstein's inequality) has a range term besides the variance, and a node
+ * left with a handful of pairs has a heavy-tailed error however small its
+ * variance.  Weights: float32 [es_mlp_num_params()]
  * = W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3.
  * Features per node: log1p d_in, log1p d_out, log1p of the mean and of the
- * max in-degree of its in-neighbours, log1p(n pi(k)^2/sum pi^2), c/d_in. */
+ * max in-degree of its in-neighbours, the mean of 1/d_in over its
+ * in-neighbours (0 for those without in-neighbours), c/d_in.  D(k,k) does
+ * not depend on the query source, and neither does any feature: a learned
+ * query computes the predictions for its graph once per loaded network and
+ * decay c, caches them in the graph (float32 [n] of device memory, freed by
+ * es_graph_destroy) and reuses them for later queries.  Learned queries on
+ * one graph from several contexts must therefore not overlap in time. */
 
 int32_t es_mlp_num_params(void);
-/* feats: device float32 [n][6] by external id; pi: device float64 [n] (es_forward). */
-es_status es_mlp_features(es_ctx* ctx, const es_graph* g, const double* pi, double c, float* feats);
+/* feats: device float32 [n][6] by external id. */
+es_status es_mlp_features(es_ctx* ctx, const es_graph* g, double c, float* feats);
 /* p_out, v_out: device float32 [N] (either may be NULL): p and v of each row of feats. */
 es_status es_mlp_infer(es_ctx* ctx, const float* weights, const float* feats, int64_t N, double c, float* p_out,
                        float* v_out);
@@ -240,12 +255,14 @@ es_status es_mlp_grad(es_ctx* ctx, const float* weights, const float* feats, con
  * nullable) gets the loss before each step (synchronizes). */
 es_status es_mlp_train(es_ctx* ctx, const float* feats, const uint64_t* R, const uint64_t* M, int64_t N, double c,
                        int32_t epochs, float lr, float* weights, float* losses);
-/* Copy the weights into the context for ES_ALLOC_LEARNED (NULL: unload). */
+/* Copy the weights into the context for ES_ALLOC_LEARNED (NULL: unload).
+ * Every call gives the context's network a new identity, so predictions
+ * cached in graphs for earlier weights are recomputed on next use. */
 es_status es_mlp_load(es_ctx* ctx, const float* weights);
 /* The weighted allocation above with a given v (device float32 [n], external
- * order): Rk device uint64 [n]. */
+ * order) and floor ratio f in [0, 1]: Rk device uint64 [n]. */
 es_status es_budget_weighted(es_ctx* ctx, const es_graph* g, const double* pi, const float* v, double R,
-                             int32_t exact_small_din, uint64_t* Rk);
+                             int32_t exact_small_din, double floor_ratio, uint64_t* Rk);
 
 /* ---- batches ------------------------------------------------------------ */
 

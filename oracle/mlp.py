@@ -9,16 +9,21 @@ variance factor.  The learned allocation keeps it, with the meeting
 probability p(k) = 1 - D(k,k) predicted by a small network from local degree
 features, v(k) = p(k)(1-p(k)), and
 
-    R(k) = ceil( (R * pi(k)^2) * (v(k) / vbar) ),
+    R(k) = ceil( (R * pi(k)^2) * (w(k) / wbar) ),  w(k) = max(v(k), f * vbar),
     vbar = (sum_k Q(pi(k)^2 v(k))) / (sum_k Q(pi(k)^2)),  Q(x) = round(x * 2^62),
+    wbar likewise with w,
 
 sums over nodes that take samples, in exact integer arithmetic, so the total
-stays that of the pi^2 rule.  The prediction only moves samples between nodes:
+stays that of the pi^2 rule.  The floor f (default 1/2) keeps every node at
+no less than about f times its pi^2 share (see budget_weighted).  The prediction only moves samples between nodes:
 every node with pi(k) > 0 still gets at least one pair (v is floored at
 V_FLOOR), so D^ stays unbiased whatever the network says.
 
 Network: 6 features -> 64 -> 64 -> 1 (ReLU), p = c * sigmoid(z), since two
-walks meet at all only if both take step 1 (probability c).  Loss: the
+walks meet at all only if both take step 1 (probability c).  D(k,k) is a
+property of the graph around v_k alone (Algorithm 2 starts both walks at
+v_k whatever the query), so every feature is source-independent and one
+prediction per node serves every query on the graph.  Loss: the
 R-weighted binomial cross-entropy of p against the observed meeting fraction
 M(k)/R(k), weights capped.
 
@@ -35,6 +40,7 @@ NF, H = 6, 64
 NPARAM = H * NF + H + H * H + H + H + 1
 V_FLOOR = 1e-6
 WEIGHT_CAP = 65536
+FLOOR_RATIO = 0.5
 
 
 def labels(R, M):
@@ -71,10 +77,12 @@ def init_params(seed: int) -> np.ndarray:
     return pack(W1, np.zeros(H), W2, np.zeros(H), w3, 0.0).astype(np.float32)
 
 
-def features(g, pi: np.ndarray, c: float) -> np.ndarray:
+def features(g, c: float) -> np.ndarray:
     """Per node: log1p d_in, log1p d_out, log1p mean and log1p max in-degree of
-    the in-neighbours, log1p(n pi^2/||pi||^2), and c/d_in (the exact probability
-    that two walks meet at step 1, Lemma 4 with l = 1)."""
+    the in-neighbours, the mean over in-neighbours a of 1/d_in(a) (0 for
+    d_in(a) = 0), and c/d_in (the exact probability that two walks meet at
+    step 1, Lemma 4 with l = 1).  Rows of nodes without in-neighbours carry
+    zeros in columns 2-5."""
     n = g.n
     din = g.din.astype(np.float64)
     dout = g.dout.astype(np.float64)
@@ -86,24 +94,20 @@ def features(g, pi: np.ndarray, c: float) -> np.ndarray:
     sums = np.bincount(row, weights=nb_din, minlength=n)
     maxs = np.zeros(n)
     np.maximum.at(maxs, row, nb_din)
+    recip = np.where(nb_din > 0, 1.0 / np.maximum(nb_din, 1.0), 0.0)
+    rsums = np.bincount(row, weights=recip, minlength=n)
     has = g.din > 0
-    mean = np.where(has, sums / np.maximum(din, 1), 0.0)
-    mx = np.where(has, maxs, 0.0)
-    F[:, 2] = np.log1p(mean)
-    F[:, 3] = np.log1p(mx)
-    p2 = pi * pi
-    tot = p2.sum()
-    F[:, 4] = np.log1p(n * p2 / tot) if tot > 0 else 0.0
+    F[:, 2] = np.log1p(np.where(has, sums / np.maximum(din, 1), 0.0))
+    F[:, 3] = np.log1p(np.where(has, maxs, 0.0))
+    F[:, 4] = np.where(has, rsums / np.maximum(din, 1), 0.0)
     F[:, 5] = np.where(has, c / np.maximum(din, 1), 0.0)
     return F
 
 
-def features_at(g, pi: np.ndarray, c: float, nodes) -> np.ndarray:
+def features_at(g, c: float, nodes) -> np.ndarray:
     """The rows of `features` for the given nodes only, one node at a time
     (for graphs too large to form every row on the CPU)."""
     nodes = np.asarray(nodes, dtype=np.int64)
-    p2 = pi * pi
-    tot = p2.sum()
     F = np.zeros((len(nodes), NF))
     for r, k in enumerate(nodes):
         d = int(g.din[k])
@@ -111,10 +115,11 @@ def features_at(g, pi: np.ndarray, c: float, nodes) -> np.ndarray:
         nb_din = g.din[nb].astype(np.float64)
         F[r, 0] = math.log1p(d)
         F[r, 1] = math.log1p(float(g.dout[k]))
-        F[r, 2] = math.log1p(nb_din.sum() / d) if d > 0 else 0.0
-        F[r, 3] = math.log1p(nb_din.max()) if d > 0 else 0.0
-        F[r, 4] = math.log1p(g.n * p2[k] / tot) if tot > 0 else 0.0
-        F[r, 5] = c / d if d > 0 else 0.0
+        if d > 0:
+            F[r, 2] = math.log1p(nb_din.sum() / d)
+            F[r, 3] = math.log1p(nb_din.max())
+            F[r, 4] = sum(1.0 / x for x in nb_din if x > 0) / d
+            F[r, 5] = c / d
     return F
 
 
@@ -169,9 +174,18 @@ def predict_variance(theta, X, c) -> np.ndarray:
     return np.maximum(p * (1 - p), V_FLOOR)
 
 
-def budget_weighted(pi, din, R, v, exact_small_din=True) -> np.ndarray:
-    """R(k) = ceil((R * (pi*pi)) * (v(k) * (S2 / S1))) with exact fixed-point sums
-    S1 = sum Q(pi^2 v), S2 = sum Q(pi^2) over nodes that take samples."""
+def budget_weighted(pi, din, R, v, exact_small_din=True, floor_ratio=FLOOR_RATIO) -> np.ndarray:
+    """R(k) = ceil((R * (pi*pi)) * (w(k) * (S2 / S3))) over the nodes that
+    take samples, with exact fixed-point sums
+
+        S1 = sum Q(pi^2 v),  S2 = sum Q(pi^2),  vbar = S1 / S2,
+        w(k) = max(v(k), floor_ratio * vbar),  S3 = sum Q(pi^2 w).
+
+    The floor keeps every node within a fixed factor of its pi^2 share:
+    Bernstein's inequality, behind the error guarantee of Theorem 1, has a
+    range term besides the variance, and a node left with very few pairs
+    has a heavy-tailed error even when its variance is small.  floor_ratio
+    = 0 gives w = v."""
     v = np.asarray(v, dtype=np.float32).astype(np.float64)
     p2 = pi * pi
     take = pi > 0
@@ -181,9 +195,13 @@ def budget_weighted(pi, din, R, v, exact_small_din=True) -> np.ndarray:
     q2 = np.rint(p2 * 2.0 ** 62).astype(np.int64)
     S1 = int(q1[take].sum())
     S2 = int(q2[take].sum())
-    vbar_inv = float(S2) / float(S1) if S1 > 0 else 1.0
+    thr = floor_ratio * (float(S1) / float(S2)) if S1 > 0 else 0.0
+    w = np.maximum(v, thr)
+    q3 = np.rint((p2 * w) * 2.0 ** 62).astype(np.int64)
+    S3 = int(q3[take].sum())
     want = R * p2
-    want = want * (v * vbar_inv) if S1 > 0 else want
+    if S3 > 0:
+        want = want * (w * (float(S2) / float(S3)))
     Rk = np.ceil(want)
     Rk[~take] = 0.0
     return Rk.astype(np.uint64)

@@ -26,6 +26,7 @@ ES_EUNSUPPORTED = -6
 ES_ALLOC_PI2 = 0
 ES_ALLOC_PI = 1
 ES_ALLOC_LEARNED = 2
+ES_LEARNED_FLOOR = 0.5  # recommended v_floor_ratio of the learned allocation
 
 ES_DEDUP = 1
 ES_DROP_SELF_LOOPS = 2
@@ -49,7 +50,7 @@ class EsError(RuntimeError):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("r_scale", ctypes.c_double), ("alloc", ctypes.c_int32), ("exact_small_din", ctypes.c_int32),
-                ("d_override", ctypes.c_void_p)]
+                ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -105,12 +106,12 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
                      ctypes.POINTER(Stats)],
         "es_batch_tuning": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "es_mlp_num_params": [],
-        "es_mlp_features": [P, P, P, dbl, P],
+        "es_mlp_features": [P, P, dbl, P],
         "es_mlp_infer": [P, P, P, i64, dbl, P, P],
         "es_mlp_grad": [P, P, P, P, P, i64, dbl, P, ctypes.POINTER(dbl)],
         "es_mlp_train": [P, P, P, P, i64, dbl, i32, ctypes.c_float, P, P],
         "es_mlp_load": [P, P],
-        "es_budget_weighted": [P, P, P, P, dbl, i32, P],
+        "es_budget_weighted": [P, P, P, P, dbl, i32, dbl, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -262,11 +263,12 @@ def es_backward(ctx: Context, g: Graph, levels, L: int, D, c: float, s):
 
 
 def make_opts(c: float, eps: float, seed: int, r_scale: float = 1.0, alloc: int = ES_ALLOC_PI2,
-              exact_small_din: bool = True, d_override=None) -> QueryOpts:
+              exact_small_din: bool = True, d_override=None, v_floor_ratio: float = ES_LEARNED_FLOOR) -> QueryOpts:
     o = QueryOpts()
     o.c, o.eps, o.seed, o.r_scale = c, eps, seed, r_scale
     o.alloc, o.exact_small_din = alloc, int(exact_small_din)
     o.d_override = None if d_override is None else d_override.data_ptr()
+    o.v_floor_ratio = v_floor_ratio
     return o
 
 
@@ -321,9 +323,9 @@ def es_mlp_num_params() -> int:
     return int(load_library().es_mlp_num_params())
 
 
-def es_mlp_features(ctx: Context, g: Graph, pi, c: float, feats):
-    _check(load_library().es_mlp_features(ctx.handle, g.handle, _ptr(pi, torch.float64, g.n, "pi"), c,
-                                          _ptr(feats, torch.float32, 6 * g.n, "feats")), ctx)
+def es_mlp_features(ctx: Context, g: Graph, c: float, feats):
+    _check(load_library().es_mlp_features(ctx.handle, g.handle, c, _ptr(feats, torch.float32, 6 * g.n, "feats")),
+           ctx)
 
 
 def es_mlp_infer(ctx: Context, weights, feats, N: int, c: float, p_out=None, v_out=None):
@@ -357,7 +359,7 @@ def es_mlp_load(ctx: Context, weights):
            ctx)
 
 
-def es_budget_weighted(ctx: Context, g: Graph, pi, v, R: float, exact_small_din: bool, Rk):
+def es_budget_weighted(ctx: Context, g: Graph, pi, v, R: float, exact_small_din: bool, floor_ratio: float, Rk):
     _check(load_library().es_budget_weighted(ctx.handle, g.handle, _ptr(pi, torch.float64, g.n, "pi"),
-                                             _ptr(v, torch.float32, g.n, "v"), R, int(exact_small_din),
+                                             _ptr(v, torch.float32, g.n, "v"), R, int(exact_small_din), floor_ratio,
                                              _ptr(Rk, torch.uint64, g.n, "Rk")), ctx)

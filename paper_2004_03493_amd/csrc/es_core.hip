@@ -592,6 +592,7 @@ es_status es_graph_destroy(es_graph* g) {
   (void)hipFree(g->dout_ext);
   (void)hipFree(g->ext_of);
   (void)hipFree(g->int_of);
+  (void)hipFree(g->vhat);
   free_plan(&g->fwd);
   free_plan(&g->back);
   delete g;

@@ -73,6 +73,12 @@ struct es_graph {
   std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> tuned;
   es::SpmvPlan fwd;            // over the out-CSR
   es::SpmvPlan back;           // over the in-CSR
+  // learned allocation: predicted variances v(k) by internal id for the
+  // network identified by vhat_net at decay vhat_c (features and network
+  // are source-independent, so one prediction serves every query)
+  mutable float* vhat = nullptr;
+  mutable uint64_t vhat_net = 0;
+  mutable double vhat_c = 0.0;
 };
 
 struct es_ctx {
@@ -89,8 +95,10 @@ struct es_ctx {
   double thr_c = -1.0;
   hipEvent_t ev[8] = {};
   hipEvent_t ev_walk_begin = nullptr;  // set while a query records stage times
-  // learned-budget network weights (device), nullptr until loaded
+  // learned-budget network weights (device), nullptr until loaded; mlp_id
+  // is unique per es_mlp_load call across all contexts (0: none loaded)
   float* mlp_w = nullptr;
+  uint64_t mlp_id = 0;
   // batch plans (tiles, descriptors, captured graph), by plan key
   es::BatchPlan* plans = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -160,7 +168,7 @@ es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* R
                                uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out);
 // Learned allocation (internal order): features, network, weighted budget.
 es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
-                                int32_t exact_small_din, uint64_t* Rk);
+                                int32_t exact_small_din, double floor_ratio, uint64_t* Rk);
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
                       double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1

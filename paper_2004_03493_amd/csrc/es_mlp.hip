@@ -13,6 +13,8 @@
 //
 // All network arithmetic is float32 on the vector ALUs: at width 64 each
 // sample is a few thousand multiply-adds against weights held in LDS.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -32,57 +34,106 @@ constexpr uint64_t kWeightCap = 65536;  // a node's weight in the loss: min(R(k)
 
 // ---- features ----------------------------------------------------------------
 
-// feats[v] for v in [0, n): k = to_int ? to_int[v] : v (internal id), pi indexed by v.
-__global__ void features_kernel(int32_t n, const int32_t* __restrict__ to_int, const int32_t* __restrict__ in_off,
-                                const int32_t* __restrict__ in_idx, const int32_t* __restrict__ din,
-                                const int32_t* __restrict__ out_off, const double* __restrict__ pi,
-                                const unsigned long long* __restrict__ pi2_sum, float c, float* __restrict__ F) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int32_t k = to_int ? to_int[v] : (int32_t)v;
-  const int32_t d = din[k];
-  const int32_t dout = out_off[k + 1] - out_off[k];
-  int64_t s = 0;
-  int32_t mx = 0;
-  for (int32_t e = in_off[k]; e < in_off[k + 1]; ++e) {
-    const int32_t dd = din[in_idx[e]];
-    s += dd;
-    mx = dd > mx ? dd : mx;
+// feats[v] for v in [0, n): k = to_int ? to_int[v] : v (internal id).  One
+// wave per node (grid-stride): the lanes stride k's in-neighbour list for the
+// integer sum and max of their in-degrees and the float64 sum of their
+// reciprocal in-degrees, reduced by a fixed butterfly, so a node's features
+// depend only on its row (identical under either id order).
+__global__ __launch_bounds__(256) void features_kernel(int32_t n, const int32_t* __restrict__ to_int,
+                                                       const int32_t* __restrict__ in_off,
+                                                       const int32_t* __restrict__ in_idx,
+                                                       const int32_t* __restrict__ din,
+                                                       const int32_t* __restrict__ out_off, float c,
+                                                       float* __restrict__ F) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nwaves) {
+    const int32_t k = to_int ? to_int[v] : (int32_t)v;
+    const int32_t b = in_off[k], e = in_off[k + 1];
+    int64_t s = 0;
+    int32_t mx = 0;
+    double rs = 0.0;
+    for (int32_t i = b + lane; i < e; i += 64) {
+      const int32_t dd = din[in_idx[i]];
+      s += dd;
+      mx = dd > mx ? dd : mx;
+      rs += dd > 0 ? 1.0 / (double)dd : 0.0;
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+      s += __shfl_xor(s, m, 64);
+      const int32_t o = __shfl_xor(mx, m, 64);
+      mx = o > mx ? o : mx;
+      rs += __shfl_xor(rs, m, 64);
+    }
+    if (lane == 0) {
+      const int32_t d = e - b;
+      const int32_t dout = out_off[k + 1] - out_off[k];
+      float* f = F + v * NF;
+      f[0] = log1pf((float)d);
+      f[1] = log1pf((float)dout);
+      f[2] = d > 0 ? log1pf((float)((double)s / (double)d)) : 0.0f;
+      f[3] = log1pf((float)mx);
+      f[4] = d > 0 ? (float)(rs / (double)d) : 0.0f;
+      f[5] = d > 0 ? c / (float)d : 0.0f;
+    }
   }
-  const double p = pi[v];
-  const double tot = (double)(*pi2_sum) * 0x1p-62;
-  float* f = F + v * NF;
-  f[0] = log1pf((float)d);
-  f[1] = log1pf((float)dout);
-  f[2] = d > 0 ? log1pf((float)((double)s / (double)d)) : 0.0f;
-  f[3] = log1pf((float)mx);
-  f[4] = tot > 0.0 ? log1pf((float)((double)n * ((p * p) / tot))) : 0.0f;
-  f[5] = d > 0 ? c / (float)d : 0.0f;
 }
 
-// S[0] += Q(pi^2 v), S[1] += Q(pi^2) over nodes that take samples (v may be NULL: S[1] only)
-__global__ void weighted_sums_kernel(int32_t n, const double* __restrict__ pi, const float* __restrict__ v,
-                                     const int32_t* __restrict__ din, int32_t exact_small_din,
-                                     unsigned long long* __restrict__ S) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+unsigned feature_blocks(const es_ctx* ctx, int32_t n) {
+  const int64_t want = ((int64_t)n + 3) / 4;  // four waves per block
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 64));
+}
+
+// S[0] += Q(pi^2 w), S[1] += Q(pi^2) over nodes that take samples, with
+// w = max(v, *thr) (thr may be NULL: w = v; v may be NULL: S[1] only).
+// Grid-stride blocks of 256 reduce in registers, then across their four
+// waves in LDS, and add once per block: integer sums, so any split gives
+// the same totals.
+__global__ __launch_bounds__(256) void weighted_sums_kernel(int32_t n, const double* __restrict__ pi,
+                                                            const float* __restrict__ v,
+                                                            const int32_t* __restrict__ din, int32_t exact_small_din,
+                                                            const double* __restrict__ thr,
+                                                            unsigned long long* __restrict__ S) {
+  __shared__ unsigned long long part[2][4];
   unsigned long long a = 0, b = 0;
-  if (k < n) {
+  const double t = thr ? *thr : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const double p = pi[k];
     const bool take = p > 0.0 && (!exact_small_din || din[k] >= 2);
     if (take) {
       const double p2 = p * p;
-      if (v) a = (unsigned long long)(int64_t)rint((p2 * (double)v[k]) * 0x1p62);
-      b = (unsigned long long)(int64_t)rint(p2 * 0x1p62);
+      if (v) {
+        double w = (double)v[k];
+        if (thr && t > w) w = t;
+        a += (unsigned long long)(int64_t)rint((p2 * w) * 0x1p62);
+      }
+      b += (unsigned long long)(int64_t)rint(p2 * 0x1p62);
     }
   }
   for (int m = 32; m > 0; m >>= 1) {
     a += __shfl_xor(a, m, 64);
     b += __shfl_xor(b, m, 64);
   }
-  if ((threadIdx.x & 63) == 0 && (a | b)) {
-    atomicAdd(&S[0], a);
-    atomicAdd(&S[1], b);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][wave] = a;
+    part[1][wave] = b;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long sa = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const unsigned long long sb = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    if (sa | sb) {
+      atomicAdd(&S[0], sa);
+      atomicAdd(&S[1], sb);
+    }
+  }
+}
+
+// thr = floor_ratio * vbar, vbar = S[0] / S[1] (0 when no node takes samples)
+__global__ void floor_kernel(const unsigned long long* __restrict__ S, double floor_ratio, double* __restrict__ thr) {
+  const int64_t s1 = (int64_t)S[0], s2 = (int64_t)S[1];
+  *thr = s1 > 0 ? floor_ratio * ((double)s1 / (double)s2) : 0.0;
 }
 
 __global__ void vbar_kernel(const unsigned long long* __restrict__ S, double* __restrict__ vbar_inv) {
@@ -90,16 +141,21 @@ __global__ void vbar_kernel(const unsigned long long* __restrict__ S, double* __
   *vbar_inv = s1 > 0 ? (double)s2 / (double)s1 : -1.0;
 }
 
-// R(k) = ceil((R * (pi*pi)) * (v * vbar_inv)); plain pi^2 rule if vbar_inv < 0
+// R(k) = ceil((R * (pi*pi)) * (max(v, thr) * vbar_inv)); plain pi^2 rule if vbar_inv < 0
 __global__ void budget_weighted_kernel(int32_t n, const double* __restrict__ pi, const float* __restrict__ v,
                                        const int32_t* __restrict__ din, double R, int32_t exact_small_din,
-                                       const double* __restrict__ vbar_inv_p, uint64_t* __restrict__ Rk) {
+                                       const double* __restrict__ thr_p, const double* __restrict__ vbar_inv_p,
+                                       uint64_t* __restrict__ Rk) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double p = pi[k];
   const double vi = *vbar_inv_p;
   double want = R * (p * p);
-  if (vi >= 0.0) want = want * ((double)v[k] * vi);
+  if (vi >= 0.0) {
+    double w = (double)v[k];
+    if (*thr_p > w) w = *thr_p;
+    want = want * (w * vi);
+  }
   uint64_t r = (uint64_t)ceil(want);
   if (!(p > 0.0)) r = 0;
   if (exact_small_din && din[k] <= 1) r = 0;
@@ -312,31 +368,49 @@ bool valid_c(double c) { return c > 0.0 && c <= 0.99; }
 
 }  // namespace
 
-// Learned budget inside a query (internal node order): features, inference,
-// exact weighted sums, then R(k).
-es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
-                                int32_t exact_small_din, uint64_t* Rk) {
-  const int32_t n = g->n;
+// The weighted allocation of R over n nodes (din indexed like pi and v).
+static es_status launch_weighted(es_ctx* ctx, int32_t n, const double* pi, const float* v, const int32_t* din, double R,
+                          int32_t exact_small_din, double floor_ratio, uint64_t* Rk) {
   es_status st;
-  auto* F = (float*)workspace(ctx, kWsFeat, sizeof(float) * NF * (size_t)n, &st);
-  if (!F) return st;
-  auto* v = (float*)workspace(ctx, kWsVhat, sizeof(float) * (size_t)n + 64, &st);
-  if (!v) return st;
   auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
   if (!S) return st;
-  double* vbar = (double*)(S + 4);
+  double* thr = (double*)(S + 4);
+  double* vbar_inv = (double*)(S + 5);
   const int tb = 256;
-  // sum of pi^2 over all nodes for the pi^2-mass feature
+  const unsigned nb = ceil_div(n, tb);
+  const unsigned nsum = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, (int64_t)ctx->num_cus * 8));
   zero_sums<<<1, 64, 0, ctx->stream>>>(S, 4);
-  weighted_sums_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, nullptr, g->din_int, 0, S + 2);
-  features_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, nullptr, g->in_off, g->in_idx, g->din_int, g->out_off,
-                                                           pi, S + 3, (float)c, F);
-  infer_kernel<<<ceil_div(n, kInferThreads), kInferThreads, 0, ctx->stream>>>(n, F, ctx->mlp_w, (float)c, nullptr, v);
-  weighted_sums_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, v, g->din_int, exact_small_din, S);
-  vbar_kernel<<<1, 1, 0, ctx->stream>>>(S, vbar);
-  budget_weighted_kernel<<<ceil_div(n, tb), tb, 0, ctx->stream>>>(n, pi, v, g->din_int, R, exact_small_din, vbar, Rk);
+  // S[0] = sum Q(pi^2 v), S[1] = sum Q(pi^2); thr = floor_ratio * S[0] / S[1]
+  weighted_sums_kernel<<<nsum, tb, 0, ctx->stream>>>(n, pi, v, din, exact_small_din, nullptr, S);
+  floor_kernel<<<1, 1, 0, ctx->stream>>>(S, floor_ratio, thr);
+  // S[2] = sum Q(pi^2 max(v, thr)), S[3] = sum Q(pi^2); vbar_inv = S[3] / S[2]
+  weighted_sums_kernel<<<nsum, tb, 0, ctx->stream>>>(n, pi, v, din, exact_small_din, thr, S + 2);
+  vbar_kernel<<<1, 1, 0, ctx->stream>>>(S + 2, vbar_inv);
+  budget_weighted_kernel<<<nb, tb, 0, ctx->stream>>>(n, pi, v, din, R, exact_small_din, thr, vbar_inv, Rk);
   ES_CHECK_HIP(ctx, hipGetLastError());
   return ES_OK;
+}
+
+// Learned budget inside a query (internal node order): predicted variances
+// (cached in the graph per network and decay), then the weighted allocation.
+es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
+                                int32_t exact_small_din, double floor_ratio, uint64_t* Rk) {
+  const int32_t n = g->n;
+  es_status st;
+  if (!g->vhat || g->vhat_net != ctx->mlp_id || g->vhat_c != c) {
+    // predictions for this network and decay: features, then inference, once
+    if (!g->vhat) ES_CHECK_HIP(ctx, hipMalloc((void**)&g->vhat, sizeof(float) * std::max<int32_t>(n, 1)));
+    auto* F = (float*)workspace(ctx, kWsFeat, sizeof(float) * NF * (size_t)n, &st);
+    if (!F) return st;
+    features_kernel<<<feature_blocks(ctx, n), 256, 0, ctx->stream>>>(n, nullptr, g->in_off, g->in_idx, g->din_int,
+                                                                     g->out_off, (float)c, F);
+    infer_kernel<<<ceil_div(n, kInferThreads), kInferThreads, 0, ctx->stream>>>(n, F, ctx->mlp_w, (float)c, nullptr,
+                                                                                g->vhat);
+    ES_CHECK_HIP(ctx, hipGetLastError());
+    g->vhat_net = ctx->mlp_id;
+    g->vhat_c = c;
+  }
+  return launch_weighted(ctx, n, pi, g->vhat, g->din_int, R, exact_small_din, floor_ratio, Rk);
 }
 
 }  // namespace es
@@ -345,18 +419,12 @@ using namespace es;
 
 extern "C" {
 
-es_status es_mlp_features(es_ctx* ctx, const es_graph* g, const double* pi, double c, float* feats) {
-  if (!ctx || !g || !pi || !feats) return ES_EINVAL;
+es_status es_mlp_features(es_ctx* ctx, const es_graph* g, double c, float* feats) {
+  if (!ctx || !g || !feats) return ES_EINVAL;
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  es_status st;
-  auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
-  if (!S) return st;
-  const int tb = 256;
-  zero_sums<<<1, 64, 0, ctx->stream>>>(S, 4);
-  weighted_sums_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, nullptr, g->din_ext, 0, S + 2);
-  features_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, g->int_of, g->in_off, g->in_idx, g->din_int,
-                                                              g->out_off, pi, S + 3, (float)c, feats);
+  features_kernel<<<feature_blocks(ctx, g->n), 256, 0, ctx->stream>>>(g->n, g->int_of, g->in_off, g->in_idx,
+                                                                      g->din_int, g->out_off, (float)c, feats);
   ES_CHECK_HIP(ctx, hipGetLastError());
   return ES_OK;
 }
@@ -438,31 +506,25 @@ es_status es_mlp_load(es_ctx* ctx, const float* weights) {
     ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ES_CHECK_HIP(ctx, hipFree(ctx->mlp_w));
     ctx->mlp_w = nullptr;
+    ctx->mlp_id = 0;
     return ES_OK;
   }
   if (!ctx->mlp_w) ES_CHECK_HIP(ctx, hipMalloc(&ctx->mlp_w, sizeof(float) * NPARAM));
   ES_CHECK_HIP(ctx, hipMemcpyAsync(ctx->mlp_w, weights, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, ctx->stream));
+  // a new identity: predictions cached in graphs for other weights go stale
+  static std::atomic<uint64_t> next_id{0};
+  ctx->mlp_id = ++next_id;
   return ES_OK;
 }
 
 es_status es_budget_weighted(es_ctx* ctx, const es_graph* g, const double* pi, const float* v, double R,
-                             int32_t exact_small_din, uint64_t* Rk) {
+                             int32_t exact_small_din, double floor_ratio, uint64_t* Rk) {
   if (!ctx || !g || !pi || !v || !Rk) return ES_EINVAL;
   if (!(R > 0.0)) return fail(ctx, ES_EINVAL, "R=%g must be positive", R);
+  if (!(floor_ratio >= 0.0 && floor_ratio <= 1.0)) return fail(ctx, ES_EINVAL, "floor ratio %g outside [0, 1]", floor_ratio);
   if (R + (double)g->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  es_status st;
-  auto* S = (unsigned long long*)workspace(ctx, kWsMlpSums, 64, &st);
-  if (!S) return st;
-  double* vbar = (double*)(S + 4);
-  const int tb = 256;
-  zero_sums<<<1, 64, 0, ctx->stream>>>(S, 2);
-  weighted_sums_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, v, g->din_ext, exact_small_din, S);
-  vbar_kernel<<<1, 1, 0, ctx->stream>>>(S, vbar);
-  budget_weighted_kernel<<<ceil_div(g->n, tb), tb, 0, ctx->stream>>>(g->n, pi, v, g->din_ext, R, exact_small_din, vbar,
-                                                                     Rk);
-  ES_CHECK_HIP(ctx, hipGetLastError());
-  return ES_OK;
+  return launch_weighted(ctx, g->n, pi, v, g->din_ext, R, exact_small_din, floor_ratio, Rk);
 }
 
 int32_t es_mlp_num_params(void) { return NPARAM; }

@@ -145,6 +145,8 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     return fail(ctx, ES_EINVAL, "unknown allocation %d", o->alloc);
   if (o->alloc == ES_ALLOC_LEARNED && !ctx->mlp_w)
     return fail(ctx, ES_EINVAL, "learned allocation requested but no network loaded");
+  if (o->alloc == ES_ALLOC_LEARNED && !(o->v_floor_ratio >= 0.0 && o->v_floor_ratio <= 1.0))
+    return fail(ctx, ES_EINVAL, "v_floor_ratio=%g outside [0, 1]", o->v_floor_ratio);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   const int32_t n = g->n;
   const int32_t L = num_levels(o->c, o->eps);
@@ -177,7 +179,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     auto* M = (uint64_t*)workspace(ctx, kWsM, sizeof(uint64_t) * (size_t)n, &st);
     if (!M) return st;
     if (o->alloc == ES_ALLOC_LEARNED)
-      ES_TRY(launch_learned_budget(ctx, g, pi, R, o->c, o->exact_small_din, Rk));
+      ES_TRY(launch_learned_budget(ctx, g, pi, R, o->c, o->exact_small_din, o->v_floor_ratio, Rk));
     else
       ES_TRY(launch_budget(ctx, g, pi, g->din_int, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
     ctx->ev_walk_begin = ev[2];  // recorded between the sample-space scan and the walk kernel

@@ -2,9 +2,9 @@
 
 Labels come from the method itself: Algorithm 2 (`es_walk_pairs`) run with a
 uniform number of pairs on every node of a training graph estimates each
-node's meeting probability 1 - D(k,k); features come from `es_mlp_features`
-with the PPR vector of a query on that graph (`es_forward`).  Training runs on
-the GPU with the library's own gradient and Adam kernels (`es_mlp_train`).
+node's meeting probability 1 - D(k,k); features come from `es_mlp_features`.
+Training runs on the GPU with the library's own gradient and Adam kernels
+(`es_mlp_train`).
 Device buffers are PyTorch tensors; every computation is a library call.
 """
 from __future__ import annotations
@@ -28,18 +28,13 @@ def init_weights(seed: int) -> np.ndarray:
     return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), w3, [0.0]]).astype(np.float32)
 
 
-def collect(ctx: es.Context, g: es.Graph, source: int, c: float, eps: float, pairs_per_node: int, seed: int):
+def collect(ctx: es.Context, g: es.Graph, c: float, pairs_per_node: int, seed: int):
     """(features [n][6] float32, R, M uint64) for every node of g, on the device."""
-    L = es.es_num_levels(c, eps)
-    lv = torch.empty((L + 1) * g.n, dtype=torch.float64, device="cuda")
-    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
-    es.es_forward(ctx, g, source, c, L, lv, pi)
     F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
-    es.es_mlp_features(ctx, g, pi, c, F)
+    es.es_mlp_features(ctx, g, c, F)
     R = torch.full((g.n,), pairs_per_node, dtype=torch.uint64, device="cuda")
     M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
     es.es_walk_pairs(ctx, g, None, R, seed, c, M)
-    del lv
     return F, R, M
 
 

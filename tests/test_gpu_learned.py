@@ -64,12 +64,9 @@ def forward_pi(es, ctx, g, u, eps=1e-4):
 @pytest.mark.parametrize("which", ["cl2k", "rmat32k"])
 def test_features_match_oracle(es, ctx, which, request):
     g, og = request.getfixturevalue(which)
-    u = int(np.argmax(og.din))
-    pi = forward_pi(es, ctx, g, u)
     F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
-    es.es_mlp_features(ctx, g, pi, C, F)
-    _, ref_pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
-    ref = mlp.features(og, ref_pi, C)
+    es.es_mlp_features(ctx, g, C, F)
+    ref = mlp.features(og, C)
     got = F.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(got - ref) <= 2e-6 * (1 + np.abs(ref)))
 
@@ -111,11 +108,12 @@ def test_weighted_budget_bitwise(es, ctx, rmat32k):
     pi = forward_pi(es, ctx, g, u)
     v = np.random.default_rng(8).uniform(1e-6, 0.25, g.n).astype(np.float32)
     R = ox.total_samples(g.n, C, 1e-4, 1e-2)
+    _, ref_pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
     for small in (True, False):
-        Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
-        es.es_budget_weighted(ctx, g, pi, torch.as_tensor(v).cuda(), R, small, Rk)
-        _, ref_pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
-        assert np.array_equal(Rk.cpu().numpy(), mlp.budget_weighted(ref_pi, og.din, R, v, small))
+        for floor in (0.0, es.ES_LEARNED_FLOOR, 1.0):
+            Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+            es.es_budget_weighted(ctx, g, pi, torch.as_tensor(v).cuda(), R, small, floor, Rk)
+            assert np.array_equal(Rk.cpu().numpy(), mlp.budget_weighted(ref_pi, og.din, R, v, small, floor))
 
 
 @pytest.fixture(scope="module")
@@ -128,8 +126,7 @@ def trained(es, ctx):
              (1 << 14,) + workloads.rmat(1 << 14, 200_000, 103)]
     for i, (n, s, d) in enumerate(specs):
         g = es.Graph(ctx, n, s, d)
-        u = int(workloads.pick_sources(n, d, 1, 7 + i)[0])
-        F, R, M = learned.collect(ctx, g, u, C, 1e-4, 4000, 1000 + i)
+        F, R, M = learned.collect(ctx, g, C, 4000, 1000 + i)
         Fs.append(F); Rs.append(R); Ms.append(M)
     F = torch.cat(Fs); R = torch.cat(Rs); M = torch.cat(Ms)
     say(f"  training rows {F.shape[0]}")
@@ -151,9 +148,8 @@ def test_trained_network_predicts_meeting_probability(es, ctx, trained, cl2k):
     g, og = cl2k
     S = sr.power_method(og, C, 60)
     p_exact = 1 - sr.exact_diagonal(og, S, C)
-    pi = forward_pi(es, ctx, g, 0)
     F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
-    es.es_mlp_features(ctx, g, pi, C, F)
+    es.es_mlp_features(ctx, g, C, F)
     p = torch.empty(g.n, dtype=torch.float32, device="cuda")
     es.es_mlp_infer(ctx, w, F, g.n, C, p, None)
     keep = og.din >= 2
@@ -199,3 +195,43 @@ def test_learned_allocation_gains_over_pi2(es, ctx, trained, cl2k):
     say(f"  MaxError pi2 {np.mean(e_p):.3e} learned {np.mean(e_l):.3e} ratio {ratio:.2f}; pairs {p_p} vs {p_l}")
     assert abs(p_l - p_p) <= 0.01 * p_p + 32 * g.n
     assert ratio > 1.15
+
+
+def test_learned_predictions_cached_per_network(es, ctx, trained, cl2k):
+    """The predicted variances are cached in the graph per loaded network and
+    decay: repeated queries agree bit for bit, other weights change the
+    allocation, reloading the first weights restores it, and another decay
+    recomputes."""
+    w, _, _ = trained
+    g, og = cl2k
+    eps = 1e-4
+    s1 = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    s2 = torch.empty_like(s1)
+
+    def run(c, out):
+        return es.es_single_source(ctx, g, 5, es.make_opts(c, eps, 9, 1e-3, alloc=es.ES_ALLOC_LEARNED), out)
+
+    es.es_mlp_load(ctx, w)
+    a = run(C, s1)
+    b = run(C, s2)
+    assert a.pairs == b.pairs and torch.equal(s1, s2)
+    other = torch.as_tensor(mlp.init_params(99)).cuda()
+    es.es_mlp_load(ctx, other)
+    o = run(C, s2)
+    assert o.pairs != a.pairs or not torch.equal(s1, s2)
+    es.es_mlp_load(ctx, w)
+    r = run(C, s2)
+    assert r.pairs == a.pairs and torch.equal(s1, s2)
+    # another decay: predictions for c = 0.8 equal those of the stage calls
+    F = torch.empty((g.n, 6), dtype=torch.float32, device="cuda")
+    es.es_mlp_features(ctx, g, 0.8, F)
+    v = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    es.es_mlp_infer(ctx, w, F, g.n, 0.8, None, v)
+    L = ox.num_levels(0.8, eps)
+    lv = torch.empty((L + 1) * g.n, dtype=torch.float64, device="cuda")
+    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_forward(ctx, g, 5, 0.8, L, lv, pi)
+    Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_budget_weighted(ctx, g, pi, v, ox.total_samples(g.n, 0.8, eps, 1e-3), True, es.ES_LEARNED_FLOOR, Rk)
+    st = run(0.8, s2)
+    assert st.pairs == int(Rk.sum())

@@ -188,10 +188,10 @@ def test_learned_allocation(es, ctx, big):
     wl, g, cg, u, L = big["wl"], big["g"], big["cg"], big["u"], big["L"]
     c = wl.c
     F = torch.empty((g.n, mlp.NF), dtype=torch.float32, device="cuda")
-    es.es_mlp_features(ctx, g, big["pi"], c, F)
+    es.es_mlp_features(ctx, g, c, F)
     rng = np.random.default_rng(4444)
     nodes = np.unique(np.concatenate([rng.integers(0, g.n, 2000), np.argsort(-cg.din)[:50]]))
-    ref_F = mlp.features_at(cg, big["ref_pi"], c, nodes)
+    ref_F = mlp.features_at(cg, c, nodes)
     got = host(F)[nodes].astype(np.float64)
     assert np.all(np.abs(got - ref_F) <= 2e-6 * (1 + np.abs(ref_F)))
     say("features match on sampled nodes")
@@ -199,14 +199,14 @@ def test_learned_allocation(es, ctx, big):
     R = ox.total_samples(g.n, c, wl.eps, R_SCALE)
     v = rng.uniform(1e-6, 0.25, g.n).astype(np.float32)
     Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
-    es.es_budget_weighted(ctx, g, big["pi"], torch.as_tensor(v).cuda(), R, True, Rk)
-    assert np.array_equal(host(Rk), mlp.budget_weighted(big["ref_pi"], cg.din, R, v, True))
+    es.es_budget_weighted(ctx, g, big["pi"], torch.as_tensor(v).cuda(), R, True, es.ES_LEARNED_FLOOR, Rk)
+    assert np.array_equal(host(Rk), mlp.budget_weighted(big["ref_pi"], cg.din, R, v, True, es.ES_LEARNED_FLOOR))
     # the learned single query equals its stages run one after another
     w = torch.as_tensor(mlp.init_params(5)).cuda()
     es.es_mlp_load(ctx, w)
     vh = torch.empty(g.n, dtype=torch.float32, device="cuda")
     es.es_mlp_infer(ctx, w, F, g.n, c, None, vh)
-    es.es_budget_weighted(ctx, g, big["pi"], vh, R, True, Rk)
+    es.es_budget_weighted(ctx, g, big["pi"], vh, R, True, es.ES_LEARNED_FLOOR, Rk)
     M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
     es.es_walk_pairs(ctx, g, None, Rk, wl.seed_walk, c, M)
     D = torch.empty(g.n, dtype=torch.float64, device="cuda")

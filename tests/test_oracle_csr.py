@@ -78,10 +78,8 @@ def test_rejects_malformed_edge_lists(bad):
 def test_features_one_node_at_a_time(name):
     from oracle import mlp
     og, cg = pair(name)
-    u = int(np.argmax(og.din))
-    _, pi = ox.forward_levels(og, u, C, ox.num_levels(C, 1e-4))
-    ref = mlp.features(og, pi, C)
+    ref = mlp.features(og, C)
     nodes = np.unique(np.concatenate([np.arange(min(og.n, 50)), np.random.default_rng(2).integers(0, og.n, 200)]))
     for g in (og, cg):
-        got = mlp.features_at(g, pi, C, nodes)
+        got = mlp.features_at(g, C, nodes)
         assert np.allclose(got, ref[nodes], rtol=1e-14, atol=1e-15)

@@ -72,10 +72,16 @@ def test_adam_constant_gradient_closed_form():
 def test_features_on_hand_built_graph():
     n, s, d = three_sources()
     g = OracleGraph(n, s, d)
-    pi = np.array([0.5, 0.1, 0.0, 0.0])
-    F = mlp.features(g, pi, C)
-    assert F[0].tolist() == pytest.approx([math.log1p(3), 0.0, 0.0, 0.0, math.log1p(4 * 0.25 / 0.26), C / 3])
-    assert F[1].tolist() == pytest.approx([0.0, math.log1p(1), 0.0, 0.0, math.log1p(4 * 0.01 / 0.26), 0.0])
+    F = mlp.features(g, C)
+    # node 0: three in-neighbours, none of which has an in-neighbour
+    assert F[0].tolist() == pytest.approx([math.log1p(3), 0.0, 0.0, 0.0, 0.0, C / 3])
+    assert F[1].tolist() == pytest.approx([0.0, math.log1p(1), 0.0, 0.0, 0.0, 0.0])
+    # 0 -> 1, 2 -> 1, 3 -> 2, 4 -> 2, 5 -> 2: I(1) = {0, 2}, d_in(0) = 0, d_in(2) = 3
+    g = OracleGraph(6, [0, 2, 3, 4, 5], [1, 1, 2, 2, 2])
+    F = mlp.features(g, C)
+    assert F[1].tolist() == pytest.approx([math.log1p(2), 0.0, math.log1p(1.5), math.log1p(3), 1 / 6, C / 2])
+    assert F[2].tolist() == pytest.approx([math.log1p(3), math.log1p(1), 0.0, 0.0, 0.0, C / 3])
+    assert F[3].tolist() == pytest.approx([0.0, math.log1p(1), 0.0, 0.0, 0.0, 0.0])
 
 
 def test_labels():
@@ -94,22 +100,53 @@ def test_weighted_budget_properties():
     R = 1e12
     base = ox.budget(pi, din, R)
     v1 = np.full(n, 0.2, dtype=np.float32)
-    r1 = mlp.budget_weighted(pi, din, R, v1)
+    r1 = mlp.budget_weighted(pi, din, R, v1, floor_ratio=0.0)
     # constant v reproduces the pi^2 rule up to the rounding of v / vbar
     assert np.abs(r1.astype(np.int64) - base.astype(np.int64)).max() <= 1
     v = rng.uniform(1e-4, 0.25, n).astype(np.float32)
-    r = mlp.budget_weighted(pi, din, R, v)
+    r = mlp.budget_weighted(pi, din, R, v, floor_ratio=0.0)
     take = (pi > 0) & (din >= 2)
     assert np.all(r[take] >= 1) and np.all(r[~take] == 0)
     # the total stays that of the pi^2 rule (ceil adds at most one per node)
     assert abs(int(r.sum()) - int(base.sum())) <= take.sum()
     # doubling v changes nothing but rounding
-    r2 = mlp.budget_weighted(pi, din, R, 2 * v)
+    r2 = mlp.budget_weighted(pi, din, R, 2 * v, floor_ratio=0.0)
     assert np.abs(r2.astype(np.int64) - r.astype(np.int64)).max() <= 1
     # nodes with larger predicted variance get more samples per unit of pi^2
     k = np.argsort(-pi * take)[:50]
     ratio = r[k] / (R * pi[k] ** 2)
     assert np.corrcoef(ratio, v[k])[0, 1] > 0.99
+
+
+def test_weighted_budget_floor():
+    rng = np.random.default_rng(6)
+    n = 5000
+    pi = rng.random(n) ** 6
+    pi[rng.random(n) < 0.2] = 0.0
+    pi /= pi.sum()
+    din = rng.integers(0, 30, n)
+    R = 1e12
+    take = (pi > 0) & (din >= 2)
+    v = (10.0 ** rng.uniform(-6, np.log10(0.25), n)).astype(np.float32)
+    base = ox.budget(pi, din, R)
+    p2 = pi * pi
+    vbar = (p2[take] * v[take]).sum() / p2[take].sum()
+    for f in (0.0, 0.125, 0.5, 1.0):
+        r = mlp.budget_weighted(pi, din, R, v, floor_ratio=f)
+        assert np.all(r[take] >= 1) and np.all(r[~take] == 0)
+        assert abs(int(r.sum()) - int(base.sum())) <= take.sum()
+        w = np.maximum(v.astype(np.float64), f * vbar)
+        wbar = (p2[take] * w[take]).sum() / p2[take].sum()
+        # every node keeps at least f * vbar / wbar of its pi^2 share
+        assert np.all(r[take] >= np.floor(f * vbar / wbar * R * p2[take] * (1 - 1e-12)))
+        # above the floor the weights stay proportional to v
+        k = np.argsort(-pi * take * (v >= f * vbar))[:50]
+        assert np.corrcoef(r[k] / (R * p2[k]), v[k])[0, 1] > 0.99
+    # a floor of one raises every node to at least vbar
+    r1 = mlp.budget_weighted(pi, din, R, v, floor_ratio=1.0)
+    small = take & (v < 0.01 * vbar) & (R * p2 > 1e4)
+    assert small.sum() > 10
+    assert np.all(r1[small] >= 0.5 * base[small])
 
 
 def test_variance_weighting_beats_pi2_with_exact_variance():
@@ -128,7 +165,8 @@ def test_variance_weighting_beats_pi2_with_exact_variance():
     R = ox.total_samples(g.n, C, eps, 1e-3)
     e_pi2, e_v = [], []
     for seed in range(4):
-        for rule, errs in ((ox.budget(pi, g.din, R), e_pi2), (mlp.budget_weighted(pi, g.din, R, v), e_v)):
+        for rule, errs in ((ox.budget(pi, g.din, R), e_pi2),
+                           (mlp.budget_weighted(pi, g.din, R, v, floor_ratio=0.0), e_v)):
             M = ox.walk_counts(g, rule, 50 + seed, C)
             s = ox.back_accumulate(g, lv, ox.diag_estimate(rule, M, g.din, C), C)
             errs.append(np.abs(s - S[:, 0]).max())
