@@ -144,11 +144,11 @@ def _walks():
         lib.oracle_lifetime_table.argtypes = [ctypes.c_double, u64p, ctypes.c_int]
         lib.oracle_lifetime_table.restype = ctypes.c_int
         lib.oracle_walk_pair.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, u64p, ctypes.c_int,
-                                         ctypes.c_uint64, ctypes.c_uint64]
+                                         ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
         lib.oracle_walk_pair.restype = ctypes.c_int
         lib.oracle_walk_counts.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p,
-                                           ctypes.c_int]
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_int]
         lib.oracle_walk_counts.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         _walk_lib = lib
@@ -176,23 +176,26 @@ def c_lifetime_thresholds(c: float) -> np.ndarray:
     return buf[: cnt + 1]
 
 
-def walk_pair(g: OracleGraph, seed: int, c: float, k: int, r: int) -> int:
+def walk_pair(g: OracleGraph, seed: int, c: float, k: int, r: int, nonstop: int = 0) -> int:
     lib = _walks()
     thr = c_lifetime_thresholds(c)
     return int(lib.oracle_walk_pair(g.in_off.ctypes.data, g.in_idx.ctypes.data, seed,
-                                    thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(thr) - 1, k, r))
+                                    thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(thr) - 1, k, r,
+                                    nonstop))
 
 
 def walk_counts(g: OracleGraph, Rk: np.ndarray, seed: int, c: float, threads: int = 0,
-                r_begin: np.ndarray | None = None) -> np.ndarray:
-    """M(k): meeting pairs among pairs r in [r_begin(k), R(k)) of each node (Algorithm 2)."""
+                r_begin: np.ndarray | None = None, nonstop: np.ndarray | None = None) -> np.ndarray:
+    """M(k): meeting pairs among pairs r in [r_begin(k), R(k)) of each node (Algorithm 2);
+    with nonstop(k) = l > 0, the non-stop pairs of Algorithm 3 (meetings after step l)."""
     lib = _walks()
     Rk = np.ascontiguousarray(Rk, dtype=np.uint64)
     M = np.zeros(g.n, dtype=np.uint64)
     rb = None if r_begin is None else np.ascontiguousarray(r_begin, dtype=np.uint64)
+    ns = None if nonstop is None else np.ascontiguousarray(nonstop, dtype=np.int32)
     rc = lib.oracle_walk_counts(g.n, g.in_off.ctypes.data, g.in_idx.ctypes.data,
-                                None if rb is None else rb.ctypes.data, Rk.ctypes.data, seed, c,
-                                M.ctypes.data, threads)
+                                None if rb is None else rb.ctypes.data, Rk.ctypes.data,
+                                None if ns is None else ns.ctypes.data, seed, c, M.ctypes.data, threads)
     if rc != 0:
         raise ValueError("oracle_walk_counts: bad arguments")
     return M

@@ -34,6 +34,13 @@
  *
  * M(k) = number of meeting pairs among r = 0 .. R(k)-1.
  *
+ * Non-stop variant (Algorithm 3, the sampling part of the local
+ * deterministic exploitation): with nonstop(k) = l > 0 both walks of every
+ * pair of node k take their first l steps without stopping (the joint
+ * lifetime becomes l + T); a meeting at a step t <= l ends the pair without
+ * counting (those meetings are accounted for exactly), meetings at t > l
+ * count as before.  l = 0 is the rule above.
+ *
  * Compile with -ffp-contract=off (no fused multiply-add anywhere).
  */
 #include <stdint.h>
@@ -94,9 +101,9 @@ int oracle_lifetime_table(double c, uint64_t* thr, int cap) {
   return t - 1;
 }
 
-/* One walk pair: returns 1 if the two walks meet, 0 otherwise. */
+/* One walk pair: returns 1 if the two walks meet (after step `nonstop`), 0 otherwise. */
 int oracle_walk_pair(const int64_t* in_off, const int32_t* in_idx, uint64_t seed, const uint64_t* thr,
-                     int tmax, uint64_t k, uint64_t r) {
+                     int tmax, uint64_t k, uint64_t r, int nonstop) {
   const uint64_t key[2] = {seed, 0};
   uint64_t life[4];
   const uint64_t life_ctr[4] = {k, r / 4, 0, 1};
@@ -104,6 +111,7 @@ int oracle_walk_pair(const int64_t* in_off, const int32_t* in_idx, uint64_t seed
   const uint64_t u = life[r % 4];
   int T = 0;
   while (T < tmax && u < thr[T + 1]) ++T;
+  T += nonstop;
   uint64_t x = k, y = k;
   uint64_t b[4];
   for (int t = 1; t <= T; ++t) {
@@ -118,16 +126,17 @@ int oracle_walk_pair(const int64_t* in_off, const int32_t* in_idx, uint64_t seed
     if (dx == 0 || dy == 0) return 0;
     x = (uint64_t)in_idx[in_off[x] + (int64_t)oracle_mulhi64(wx, dx)];
     y = (uint64_t)in_idx[in_off[y] + (int64_t)oracle_mulhi64(wy, dy)];
-    if (x == y) return 1;
+    if (x == y) return t > nonstop ? 1 : 0;
   }
   return 0;
 }
 
 /* M[k] = number of meeting pairs among pairs r in [r_begin[k], r_end[k]) of
- * node k, for k = 0..n-1 (r_begin may be NULL, meaning 0).  Returns 0, or -1
- * if c is outside (0, 1). */
+ * node k, for k = 0..n-1 (r_begin may be NULL, meaning 0; nonstop may be
+ * NULL, meaning 0 for every node).  Returns 0, or -1 if c is outside (0, 1). */
 int oracle_walk_counts(int64_t n, const int64_t* in_off, const int32_t* in_idx, const uint64_t* r_begin,
-                       const uint64_t* r_end, uint64_t seed, double c, uint64_t* M, int threads) {
+                       const uint64_t* r_end, const int32_t* nonstop, uint64_t seed, double c, uint64_t* M,
+                       int threads) {
   if (!(c > 0.0 && c < 1.0)) return -1;
   uint64_t* thr = (uint64_t*)malloc(sizeof(uint64_t) * (ORACLE_TMAX + 1));
   int tmax = oracle_lifetime_table(c, thr, ORACLE_TMAX + 1);
@@ -141,7 +150,9 @@ int oracle_walk_counts(int64_t n, const int64_t* in_off, const int32_t* in_idx, 
     uint64_t b = r_begin ? r_begin[k] : 0, e = r_end[k];
     if (e <= b || e - b >= big) continue;
     uint64_t cnt = 0;
-    for (uint64_t r = b; r < e; ++r) cnt += (uint64_t)oracle_walk_pair(in_off, in_idx, seed, thr, tmax, (uint64_t)k, r);
+    const int l = nonstop ? nonstop[k] : 0;
+    for (uint64_t r = b; r < e; ++r)
+      cnt += (uint64_t)oracle_walk_pair(in_off, in_idx, seed, thr, tmax, (uint64_t)k, r, l);
     M[k] = cnt;
   }
   /* nodes with many pairs: split the pairs over threads */
@@ -153,9 +164,10 @@ int oracle_walk_counts(int64_t n, const int64_t* in_off, const int32_t* in_idx, 
     }
     if (e - b < big) continue;
     uint64_t cnt = 0;
+    const int l = nonstop ? nonstop[k] : 0;
 #pragma omp parallel for schedule(static) reduction(+ : cnt)
     for (int64_t r = (int64_t)b; r < (int64_t)e; ++r)
-      cnt += (uint64_t)oracle_walk_pair(in_off, in_idx, seed, thr, tmax, (uint64_t)k, (uint64_t)r);
+      cnt += (uint64_t)oracle_walk_pair(in_off, in_idx, seed, thr, tmax, (uint64_t)k, (uint64_t)r, l);
     M[k] = cnt;
   }
   free(thr);
