@@ -86,7 +86,15 @@ typedef struct {
   const double* d_override;  /* device [n] or NULL: use this diagonal instead of sampling   */
   double v_floor_ratio;      /* ES_ALLOC_LEARNED: floor f in [0, 1] on v(k) / vbar (below;
                                 ES_LEARNED_FLOOR = 1/2 recommended, 0 = none)              */
+  int32_t lde;               /* local deterministic exploitation (Algorithm 3; below):
+                                ES_LDE_OFF, ES_LDE_AS_PRINTED or ES_LDE_REDUCED            */
 } es_query_opts;
+
+typedef enum {
+  ES_LDE_OFF = 0,         /* Algorithm 2 for every node                                   */
+  ES_LDE_AS_PRINTED = 1,  /* Algorithm 3 with R(k) non-stop pairs                         */
+  ES_LDE_REDUCED = 2      /* Algorithm 3 with ceil(R(k) c^l(k)) non-stop pairs            */
+} es_lde_mode;
 
 #define ES_LEARNED_FLOOR 0.5
 
@@ -104,6 +112,8 @@ typedef struct {
   float ms_walk;             /*   the walk-pair kernel alone                         */
   float ms_diag;             /*   diagonal estimate                                  */
   float ms_backward;         /*   back-accumulation                                  */
+  int32_t lde_source_level;  /* l(u) of the source under Algorithm 3 (0 when off)    */
+  double lde_source_zsum;    /* sum_{l <= l(u)} Z_l(u), the source's exact part      */
 } es_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -209,6 +219,38 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
  * [k] or NULL.  Errors: ES_EINVAL (k < 1, k > n - (exclude >= 0)). */
 es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                   double* val_out);
+
+/* ---- local deterministic exploitation (Section 3.3, Algorithm 3) ----------
+ * Z_l(k) is the probability that two sqrt(c)-walks from v_k first meet at
+ * step l (Lemma 4 gives it from the transition probabilities), and
+ * D(k,k) = 1 - sum_l Z_l(k).  Algorithm 3 computes Z_1..Z_l(k) exactly and
+ * estimates the rest with R'(k) pairs of walks that do not stop during their
+ * first l(k) steps (sqrt(c)-walks afterwards); M(k) counts those meeting
+ * after step l(k) without meeting before:
+ *   D^(k,k) = (1 - sum_{l <= l(k)} Z_l(k)) - c^l(k) M(k) / R'(k).
+ * l(k) is the largest level whose deterministic work E_l(k) (in-walks of
+ * length <= l from v_k) stays within 2 R(k) / sqrt(c); at most min(3, L) for
+ * the query source u and 1 for every other node.  R'(k) = R(k)
+ * (ES_LDE_AS_PRINTED, smaller variance) or ceil(R(k) c^l(k)) (ES_LDE_REDUCED:
+ * every pair weighs at most 1/R(k) and has Bernoulli variance at most 1/4,
+ * so the Bernstein bound of Theorem 1 holds as for R(k) plain pairs). */
+
+/* levels: device float64 [(L+1) n] from es_forward for source u (only levels
+ * 0..min(3, L) are read); Rk: device uint64 [n] (es_budget).  Writes, by
+ * external id: ell (device int32 [n]) = l(k), zsum (device float64 [n]) =
+ * sum_{l <= l(k)} Z_l(k), Rk_out (device uint64 [n]) = R'(k).  mode:
+ * es_lde_mode (ES_LDE_OFF gives l = 0 and R' = R).  Synchronizes once. */
+es_status es_lde_plan(es_ctx* ctx, const es_graph* g, int32_t u, const double* levels, int32_t L, const uint64_t* Rk,
+                      double c, int32_t mode, int32_t* ell, double* zsum, uint64_t* Rk_out);
+/* Algorithm 3's sampling: es_walk_pairs with the pairs of node k taking
+ * ell[k] (device int32 [n], 0..L) non-stop steps first; a meeting at a step
+ * t <= ell[k] ends the pair uncounted, the joint lifetime is ell[k] + T. */
+es_status es_walk_pairs_lde(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                            const int32_t* ell, uint64_t seed, double c, uint64_t* M);
+/* D^ above where ell[k] > 0, (R - M)/R where ell[k] = 0, the exact values of
+ * es_diag for d_in <= 1 with exact_small_din. */
+es_status es_diag_lde(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* ell,
+                      const double* zsum, double c, int32_t exact_small_din, double* D);
 
 /* ---- learned walk budget --------------------------------------------------
  * Lemma 1 (Section 3.1) bounds the variance of s^L(j) by a sum over nodes k of

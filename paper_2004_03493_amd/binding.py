@@ -26,6 +26,7 @@ ES_EUNSUPPORTED = -6
 ES_ALLOC_PI2 = 0
 ES_ALLOC_PI = 1
 ES_ALLOC_LEARNED = 2
+ES_LDE_OFF, ES_LDE_AS_PRINTED, ES_LDE_REDUCED = 0, 1, 2
 ES_LEARNED_FLOOR = 0.5  # recommended v_floor_ratio of the learned allocation
 
 ES_DEDUP = 1
@@ -37,7 +38,7 @@ SYMBOLS = (
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
     "es_backward", "es_single_source", "es_topk", "es_batch", "es_batch_tuning",
     "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
-    "es_budget_weighted",
+    "es_budget_weighted", "es_lde_plan", "es_walk_pairs_lde", "es_diag_lde",
 )
 
 
@@ -50,7 +51,7 @@ class EsError(RuntimeError):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("r_scale", ctypes.c_double), ("alloc", ctypes.c_int32), ("exact_small_din", ctypes.c_int32),
-                ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double)]
+                ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double), ("lde", ctypes.c_int32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -64,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("philox_blocks", ctypes.c_uint64),
                 ("walk_steps", ctypes.c_uint64), ("ms_forward", ctypes.c_float),
                 ("ms_budget", ctypes.c_float), ("ms_walk", ctypes.c_float), ("ms_diag", ctypes.c_float),
-                ("ms_backward", ctypes.c_float)]
+                ("ms_backward", ctypes.c_float), ("lde_source_level", ctypes.c_int32),
+                ("lde_source_zsum", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -112,6 +114,9 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_mlp_train": [P, P, P, P, i64, dbl, i32, ctypes.c_float, P, P],
         "es_mlp_load": [P, P],
         "es_budget_weighted": [P, P, P, P, dbl, i32, dbl, P],
+        "es_lde_plan": [P, P, i32, P, i32, P, dbl, i32, P, P, P],
+        "es_walk_pairs_lde": [P, P, P, P, P, u64, dbl, P],
+        "es_diag_lde": [P, P, P, P, P, P, dbl, i32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -263,12 +268,14 @@ def es_backward(ctx: Context, g: Graph, levels, L: int, D, c: float, s):
 
 
 def make_opts(c: float, eps: float, seed: int, r_scale: float = 1.0, alloc: int = ES_ALLOC_PI2,
-              exact_small_din: bool = True, d_override=None, v_floor_ratio: float = ES_LEARNED_FLOOR) -> QueryOpts:
+              exact_small_din: bool = True, d_override=None, v_floor_ratio: float = ES_LEARNED_FLOOR,
+              lde: int = ES_LDE_OFF) -> QueryOpts:
     o = QueryOpts()
     o.c, o.eps, o.seed, o.r_scale = c, eps, seed, r_scale
     o.alloc, o.exact_small_din = alloc, int(exact_small_din)
     o.d_override = None if d_override is None else d_override.data_ptr()
     o.v_floor_ratio = v_floor_ratio
+    o.lde = lde
     return o
 
 
@@ -363,3 +370,24 @@ def es_budget_weighted(ctx: Context, g: Graph, pi, v, R: float, exact_small_din:
     _check(load_library().es_budget_weighted(ctx.handle, g.handle, _ptr(pi, torch.float64, g.n, "pi"),
                                              _ptr(v, torch.float32, g.n, "v"), R, int(exact_small_din), floor_ratio,
                                              _ptr(Rk, torch.uint64, g.n, "Rk")), ctx)
+
+
+def es_lde_plan(ctx: Context, g: Graph, u: int, levels, L: int, Rk, c: float, mode: int, ell, zsum, Rk_out):
+    _check(load_library().es_lde_plan(ctx.handle, g.handle, u, _ptr(levels, torch.float64, (L + 1) * g.n, "levels"),
+                                      L, _ptr(Rk, torch.uint64, g.n, "Rk"), c, mode,
+                                      _ptr(ell, torch.int32, g.n, "ell"), _ptr(zsum, torch.float64, g.n, "zsum"),
+                                      _ptr(Rk_out, torch.uint64, g.n, "Rk_out")), ctx)
+
+
+def es_walk_pairs_lde(ctx: Context, g: Graph, r_begin, r_end, ell, seed: int, c: float, M):
+    _check(load_library().es_walk_pairs_lde(ctx.handle, g.handle, _ptr(r_begin, torch.uint64, g.n, "r_begin"),
+                                            _ptr(r_end, torch.uint64, g.n, "r_end"),
+                                            _ptr(ell, torch.int32, g.n, "ell"), seed, c,
+                                            _ptr(M, torch.uint64, g.n, "M")), ctx)
+
+
+def es_diag_lde(ctx: Context, g: Graph, Rk, M, ell, zsum, c: float, exact_small_din: bool, D):
+    _check(load_library().es_diag_lde(ctx.handle, g.handle, _ptr(Rk, torch.uint64, g.n, "Rk"),
+                                      _ptr(M, torch.uint64, g.n, "M"), _ptr(ell, torch.int32, g.n, "ell"),
+                                      _ptr(zsum, torch.float64, g.n, "zsum"), c, int(exact_small_din),
+                                      _ptr(D, torch.float64, g.n, "D")), ctx)

@@ -132,6 +132,13 @@ enum Slot : int {
   kWsMlpAcc,
   kWsMlpGrad,
   kWsMlpLoss,
+  kWsLdeEll,
+  kWsLdeZ,
+  kWsLdeR,
+  kWsLdeW,
+  kWsLdeMisc,
+  kWsLdeLv,
+  kWsLdeRin,
   kWsCount
 };
 
@@ -160,8 +167,10 @@ es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const 
                         int32_t alloc, int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk);
 // Walk pairs over sample counts indexed by internal ids (external_counts = false)
 // or by external ids (external_counts = true); M is indexed like the counts.
+// nonstop (indexed like the counts, or NULL): the non-stop pairs of Algorithm 3.
 es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
-                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out);
+                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out,
+                       const int32_t* nonstop = nullptr);
 // Shared samples of a block of B sources: Rmax[k] pairs per internal node k,
 // meetings bucketed by T (ascending thresholds per node, stride B) into H[k * B + j].
 es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
@@ -171,6 +180,20 @@ es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi
                                 int32_t exact_small_din, double floor_ratio, uint64_t* Rk);
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
                       double c, int32_t exact_small_din, double* D);
+
+// Local deterministic exploitation (Algorithm 3), internal order.  lv: forward
+// levels pi^0..pi^L of source u (internal id); Rk: budget.  Writes l(k), the
+// exact part sum_{l <= l(k)} Z_l(k) and the pair counts R'(k); *level_u and
+// *zsum_u (host, nullable) receive the source's values (synchronizes).
+struct LdeOut {
+  int32_t* ell;
+  double* zsum;
+  uint64_t* Rk2;
+};
+es_status launch_lde(es_ctx* ctx, const es_graph* g, int32_t u, const double* lv, int32_t L, const uint64_t* Rk,
+                     double c, int32_t mode, LdeOut out, int32_t* level_u, double* zsum_u);
+es_status launch_diag_lde(es_ctx* ctx, int32_t n, const uint64_t* Rk, const uint64_t* M, const int32_t* ell,
+                          const double* zsum, const int32_t* din, double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1
 es_status launch_permute_f64(es_ctx* ctx, int32_t n, int32_t rows, const double* src, const int32_t* map, double* dst);
 es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,

@@ -104,6 +104,20 @@ es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin,
   return ES_OK;
 }
 
+es_status es_walk_pairs_lde(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
+                            const int32_t* ell, uint64_t seed, double c, uint64_t* M) {
+  if (!ctx || !g || !r_end || !ell || !M) return ES_EINVAL;
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  WalkTotals* tot = nullptr;
+  ES_TRY(launch_walks(ctx, g, r_begin, r_end, seed, c, M, true, &tot, ell));
+  WalkTotals h;
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h.overflow) return fail(ctx, ES_EOVERFLOW, "sample count reaches 2^63");
+  return ES_OK;
+}
+
 es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
                   int32_t exact_small_din, double* D) {
   if (!ctx || !g || !Rk || !M || !D) return ES_EINVAL;
@@ -147,6 +161,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     return fail(ctx, ES_EINVAL, "learned allocation requested but no network loaded");
   if (o->alloc == ES_ALLOC_LEARNED && !(o->v_floor_ratio >= 0.0 && o->v_floor_ratio <= 1.0))
     return fail(ctx, ES_EINVAL, "v_floor_ratio=%g outside [0, 1]", o->v_floor_ratio);
+  if (o->lde < 0 || o->lde > 2) return fail(ctx, ES_EINVAL, "lde=%d outside 0..2", o->lde);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   const int32_t n = g->n;
   const int32_t L = num_levels(o->c, o->eps);
@@ -173,6 +188,8 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   ES_TRY(launch_forward(ctx, g, g->h_int_of[u], o->c, L, levels, pi, q0, q1));
   ES_CHECK_HIP(ctx, hipEventRecord(ev[1], ctx->stream));
   WalkTotals* tot = nullptr;
+  int32_t lde_level = 0;
+  double lde_zsum = 0.0;
   if (!o->d_override) {
     auto* Rk = (uint64_t*)workspace(ctx, kWsRk, sizeof(uint64_t) * (size_t)n, &st);
     if (!Rk) return st;
@@ -182,12 +199,29 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
       ES_TRY(launch_learned_budget(ctx, g, pi, R, o->c, o->exact_small_din, o->v_floor_ratio, Rk));
     else
       ES_TRY(launch_budget(ctx, g, pi, g->din_int, R, o->alloc, o->exact_small_din, nullptr, 0.0, Rk));
+    const uint64_t* Rwalk = Rk;
+    LdeOut lo{nullptr, nullptr, nullptr};
+    if (o->lde) {
+      // Algorithm 3: exact first levels, then non-stop pairs on R'(k)
+      lo.ell = (int32_t*)workspace(ctx, kWsLdeEll, sizeof(int32_t) * (size_t)n, &st);
+      if (!lo.ell) return st;
+      lo.zsum = (double*)workspace(ctx, kWsLdeZ, sizeof(double) * (size_t)n, &st);
+      if (!lo.zsum) return st;
+      lo.Rk2 = (uint64_t*)workspace(ctx, kWsLdeR, sizeof(uint64_t) * (size_t)n, &st);
+      if (!lo.Rk2) return st;
+      ES_TRY(launch_lde(ctx, g, g->h_int_of[u], levels, L, Rk, o->c, o->lde, lo, &lde_level,
+                        stats ? &lde_zsum : nullptr));
+      Rwalk = lo.Rk2;
+    }
     ctx->ev_walk_begin = ev[2];  // recorded between the sample-space scan and the walk kernel
-    const es_status ws = launch_walks(ctx, g, nullptr, Rk, o->seed, o->c, M, false, &tot);
+    const es_status ws = launch_walks(ctx, g, nullptr, Rwalk, o->seed, o->c, M, false, &tot, lo.ell);
     ctx->ev_walk_begin = nullptr;
     ES_TRY(ws);
     ES_CHECK_HIP(ctx, hipEventRecord(ev[3], ctx->stream));
-    ES_TRY(launch_diag(ctx, g, Rk, M, g->din_int, o->c, o->exact_small_din, Dh));
+    if (o->lde)
+      ES_TRY(launch_diag_lde(ctx, n, Rwalk, M, lo.ell, lo.zsum, g->din_int, o->c, o->exact_small_din, Dh));
+    else
+      ES_TRY(launch_diag(ctx, g, Rk, M, g->din_int, o->c, o->exact_small_din, Dh));
     ES_CHECK_HIP(ctx, hipEventRecord(ev[4], ctx->stream));
   } else {
     ES_CHECK_HIP(ctx, hipEventRecord(ev[2], ctx->stream));
@@ -218,6 +252,8 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_walk, ev[2], ev[3]));
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_diag, ev[3], ev[4]));
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_backward, ev[4], ev[5]));
+    s.lde_source_level = lde_level;
+    s.lde_source_zsum = lde_zsum;
     *stats = s;
   }
   return ES_OK;

@@ -292,6 +292,7 @@ struct WalkArgs {
   const uint64_t* __restrict__ T;      // buckets only: ascending thresholds of each index, stride B
   int32_t B;
   uint64_t seed;
+  const int32_t* __restrict__ nonstop;  // non-stop variant only: l(k) per count index
 };
 
 // One step of both walks; returns 1 = met, 0 = moved without meeting, -1 = a walk is stuck.
@@ -325,9 +326,12 @@ __device__ __forceinline__ void flush_work(WalkTotals* tot, uint32_t nblocks, ui
 // the block's per-source sample counts R_b(k) in ascending order; source b then
 // owns the meetings of buckets j <= #{b' : R_b'(k) < R_b(k)}, i.e. exactly the
 // meetings among its own pairs r < R_b(k).
+// kNonstop = true (Algorithm 3): the pairs of count index k take their first
+// l = nonstop[k] steps without stopping (lifetime l + T), and a meeting at a
+// step t <= l ends the pair without counting.
 // Eight waves per SIMD (at most 64 VGPRs) measured faster than the looser
 // register budget the compiler picks by itself, despite a few spills.
-template <bool kBuckets>
+template <bool kBuckets, bool kNonstop>
 __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void walk_pairs_kernel(
     WalkArgs a) {
   const int lane = threadIdx.x & 63;
@@ -388,6 +392,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     }
     bool in_pair = false;
     int32_t k = 0, x = 0, y = 0, t = 0, T = 0, kg = 0;
+    int32_t nsl = 0;  // non-stop steps of the current pair
     uint64_t r = 0, kc = 0;
     for (;;) {
       // out of a pair: start the next one; pairs whose cached lifetime is 0
@@ -405,8 +410,12 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
           }
           const uint64_t rr = prb + (i - pbeg);
           if (pk == lk && (rr >> 2) == lq) {
-            const int32_t TT = (int32_t)((lt >> (16 * (rr & 3))) & 0xffffu);
+            int32_t TT = (int32_t)((lt >> (16 * (rr & 3))) & 0xffffu);
             ++i;
+            if constexpr (kNonstop) {
+              nsl = a.nonstop[pk];
+              TT += nsl;
+            }
             if (TT == 0) continue;  // both walks stop at once: no meeting
             k = pk;
             r = rr;
@@ -445,10 +454,16 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
       t += 1;
       ++nsteps;
+      if constexpr (kNonstop) {
+        if (st > 0 && t <= nsl) st = -1;  // met during the exact levels: not counted
+      }
       if (st == 0 && t < T) {
         st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
         t += 1;
         ++nsteps;
+        if constexpr (kNonstop) {
+          if (st > 0 && t <= nsl) st = -1;
+        }
       }
       const int res = st != 0 ? st : (t >= T ? -1 : 0);  // 1: met, -1: ended, 0: go on
       if (res != 0) {
@@ -531,7 +546,7 @@ namespace {
 
 es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end, uint64_t seed,
                      double c, unsigned long long* M, int64_t m_len, bool external_counts, const uint64_t* T,
-                     int32_t B, WalkTotals** totals_out) {
+                     int32_t B, const int32_t* nonstop, WalkTotals** totals_out) {
   const int32_t n = g->n;
   es_status st;
   ES_TRY(lifetime_table(ctx, c));
@@ -566,10 +581,12 @@ es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, co
   a.T = T;
   a.B = B;
   a.seed = seed;
+  a.nonstop = nonstop;
   const int grid = ctx->num_cus * 8;
   if (ctx->ev_walk_begin) ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev_walk_begin, ctx->stream));
-  if (T) walk_pairs_kernel<true><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
-  else walk_pairs_kernel<false><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  if (T) walk_pairs_kernel<true, false><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  else if (nonstop) walk_pairs_kernel<false, true><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
+  else walk_pairs_kernel<false, false><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
   ES_CHECK_HIP(ctx, hipGetLastError());
   if (totals_out) *totals_out = tot;
   return ES_OK;
@@ -578,15 +595,16 @@ es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, co
 }  // namespace
 
 es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
-                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out) {
+                       uint64_t seed, double c, uint64_t* M, bool external_counts, WalkTotals** totals_out,
+                       const int32_t* nonstop) {
   return walks_core(ctx, g, r_begin, r_end, seed, c, (unsigned long long*)M, g->n, external_counts, nullptr, 1,
-                    totals_out);
+                    nonstop, totals_out);
 }
 
 es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
                                uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out) {
   return walks_core(ctx, g, nullptr, Rmax, seed, c, (unsigned long long*)H, (int64_t)g->n * B, false, T, B,
-                    totals_out);
+                    nullptr, totals_out);
 }
 
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,

@@ -1,0 +1,201 @@
+"""GPU local deterministic exploitation (Section 3.3, Algorithm 3, Lemma 4)
+against the oracle: the level plan, the non-stop walk pairs, the estimator,
+whole queries, and accuracy against the Power Method."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from graphs import hub_graph, random_graph
+from oracle import exactsim as ox
+from oracle import lde
+from oracle import simrank as sr
+from oracle.graph import OracleGraph
+
+pytestmark = pytest.mark.gpu
+
+C = 0.6
+S_TOL = 1e-9
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+@pytest.fixture(scope="module")
+def es():
+    from paper_2004_03493_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(es):
+    c = es.Context(0)
+    yield c
+    c.close()
+
+
+GRAPHS = {
+    "chung_lu_2k": lambda: (2000,) + workloads.chung_lu(2000, 20000, 11),
+    "rmat_32k": lambda: (1 << 15,) + workloads.rmat(1 << 15, 500_000, 5),
+    "hubs": lambda: hub_graph(30000, 20000, 20000, 60000, 3),
+    "random_small": lambda: random_graph(50, 200, 1),
+}
+_cache = {}
+
+
+def pair(es, ctx, name):
+    if name not in _cache:
+        n, s, d = GRAPHS[name]()
+        say(f"[graph {name}]")
+        _cache[name] = (es.Graph(ctx, n, s, d), OracleGraph(n, s, d))
+    return _cache[name]
+
+
+def stages(es, ctx, g, og, u, eps, r_scale):
+    """GPU forward levels and budget, with the oracle's own (bitwise equal)."""
+    L = ox.num_levels(C, eps)
+    lv = torch.empty((L + 1) * g.n, dtype=torch.float64, device="cuda")
+    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_forward(ctx, g, u, C, L, lv, pi)
+    R = ox.total_samples(g.n, C, eps, r_scale)
+    Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_budget(ctx, g, pi, R, es.ES_ALLOC_PI2, True, Rk)
+    ref_lv, ref_pi = ox.forward_levels(og, u, C, L)
+    ref_R = ox.budget(ref_pi, og.din, R, True)
+    assert np.array_equal(host(Rk), ref_R)
+    return L, lv, Rk, ref_lv, ref_R
+
+
+def gpu_plan(es, ctx, g, u, lv, L, Rk, mode):
+    ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    zsum = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_lde_plan(ctx, g, u, lv, L, Rk, C, mode, ell, zsum, R2)
+    return ell, zsum, R2
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_plan_matches_oracle(es, ctx, name):
+    g, og = pair(es, ctx, name)
+    for u in sorted({int(np.argmax(og.din)), int(np.argsort(og.din)[len(og.din) // 2]), 3}):
+        for r_scale in (1e-6, 1e-3, 1e-1):
+            L, lv, Rk, _, ref_R = stages(es, ctx, g, og, u, 1e-4, r_scale)
+            for mode in (lde.MODE_OFF, lde.MODE_AS_PRINTED, lde.MODE_REDUCED):
+                ell, zsum, R2 = gpu_plan(es, ctx, g, u, lv, L, Rk, mode)
+                r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, C, mode, source_max=min(3, L))
+                assert np.array_equal(host(ell), r_ell)
+                assert np.array_equal(host(R2), r_R2)
+                gz = host(zsum)
+                others = np.arange(g.n) != u
+                assert np.array_equal(gz[others].view(np.uint64), r_z[others].view(np.uint64))
+                assert abs(gz[u] - r_z[u]) <= 1e-13 * max(1.0, abs(r_z[u]))
+            say(f"  u={u} r_scale={r_scale:g}: l(u)={int(r_ell[u])} zsum(u)={r_z[u]:.6g}")
+
+
+@pytest.mark.parametrize("name", ["chung_lu_2k", "rmat_32k", "hubs"])
+def test_nonstop_walks_bitwise(es, ctx, name):
+    g, og = pair(es, ctx, name)
+    rng = np.random.default_rng(8)
+    R = rng.integers(0, 500, g.n).astype(np.uint64)
+    R[rng.random(g.n) < 0.3] = 0
+    R[int(np.argmax(og.din))] = 200_000
+    ell = rng.integers(0, 4, g.n).astype(np.int32)
+    M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_walk_pairs_lde(ctx, g, None, dev(R, torch.uint64), dev(ell, torch.int32), 41, C, M)
+    assert np.array_equal(host(M), ox.walk_counts(og, R, 41, C, nonstop=ell))
+    # ranges split like the plain pairs
+    lo = (R // 3).astype(np.uint64)
+    Ma = torch.empty_like(M)
+    Mb = torch.empty_like(M)
+    es.es_walk_pairs_lde(ctx, g, None, dev(lo, torch.uint64), dev(ell, torch.int32), 41, C, Ma)
+    es.es_walk_pairs_lde(ctx, g, dev(lo, torch.uint64), dev(R, torch.uint64), dev(ell, torch.int32), 41, C, Mb)
+    assert np.array_equal(host(Ma) + host(Mb), host(M))
+    # l = 0 everywhere is Algorithm 2
+    M0 = torch.empty_like(M)
+    es.es_walk_pairs(ctx, g, None, dev(R, torch.uint64), 41, C, M0)
+    es.es_walk_pairs_lde(ctx, g, None, dev(R, torch.uint64), dev(np.zeros(g.n, np.int32), torch.int32), 41, C, Ma)
+    assert torch.equal(M0, Ma)
+
+
+def test_diag_lde_bitwise(es, ctx):
+    g, og = pair(es, ctx, "chung_lu_2k")
+    rng = np.random.default_rng(9)
+    R = rng.integers(0, 1000, g.n).astype(np.uint64)
+    M = (R.astype(np.float64) * rng.uniform(0, 0.5, g.n)).astype(np.uint64)
+    ell = rng.integers(0, 4, g.n).astype(np.int32)
+    zsum = rng.uniform(0, 0.3, g.n)
+    for small in (True, False):
+        D = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        es.es_diag_lde(ctx, g, dev(R, torch.uint64), dev(M, torch.uint64), dev(ell, torch.int32),
+                       dev(zsum, torch.float64), C, small, D)
+        ref = lde.diag_estimate(R, M, ell, zsum, C, og.din, small)
+        assert np.array_equal(host(D).view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name", ["chung_lu_2k", "rmat_32k"])
+def test_single_source_equals_stages_and_oracle(es, ctx, name, mode):
+    g, og = pair(es, ctx, name)
+    u = int(np.argmax(og.din))
+    eps, r_scale, seed = 1e-4, 1e-3, 77
+    L, lv, Rk, ref_lv, ref_R = stages(es, ctx, g, og, u, eps, r_scale)
+    ell, zsum, R2 = gpu_plan(es, ctx, g, u, lv, L, Rk, mode)
+    M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_walk_pairs_lde(ctx, g, None, R2, ell, seed, C, M)
+    D = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_diag_lde(ctx, g, R2, M, ell, zsum, C, True, D)
+    s_st = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_backward(ctx, g, lv, L, D, C, s_st)
+    s_q = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, seed, r_scale, lde=mode), s_q)
+    assert torch.equal(s_q, s_st)
+    assert st.pairs == int(host(R2).sum())
+    assert st.lde_source_level == int(host(ell)[u])
+    # the oracle end to end
+    r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, C, mode, source_max=min(3, L))
+    r_M = ox.walk_counts(og, r_R2, seed, C, nonstop=r_ell)
+    assert np.array_equal(host(M), r_M)
+    r_D = lde.diag_estimate(r_R2, r_M, r_ell, r_z, C, og.din)
+    r_s = ox.back_accumulate(og, ref_lv, r_D, C)
+    err = np.abs(host(s_q) - r_s).max()
+    say(f"  l(u)={st.lde_source_level} zsum(u)={st.lde_source_zsum:.6g} pairs {st.pairs} "
+        f"(plain {int(ref_R.sum())}) max|s - oracle| {err:.1e}")
+    assert err <= S_TOL
+    assert abs(st.lde_source_zsum - r_z[u]) <= 1e-13
+
+
+def test_accuracy_against_power_method(es, ctx):
+    """Algorithm 3 as printed lowers MaxError at equal pairs; the reduced
+    sample count keeps MaxError near Algorithm 2's with fewer pairs."""
+    g, og = pair(es, ctx, "chung_lu_2k")
+    S = sr.power_method(og, C, 60)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eps = 1e-4
+    err = {0: [], 1: [], 2: []}
+    pairs = {0: 0, 1: 0, 2: 0}
+    for u in (0, 5, 50, 300):
+        for seed in range(6):
+            for mode in (0, 1, 2):
+                st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, 500 + seed, 1e-3, lde=mode), s)
+                err[mode].append(sr.max_error(host(s), S[:, u]))
+                pairs[mode] += st.pairs
+    m = {k: float(np.mean(v)) for k, v in err.items()}
+    say(f"  MaxError plain {m[0]:.3e} as printed {m[1]:.3e} reduced {m[2]:.3e}; "
+        f"pairs {pairs[0]} {pairs[1]} {pairs[2]}")
+    assert pairs[1] == pairs[0]
+    assert pairs[2] < 0.8 * pairs[0]
+    assert m[1] < m[0]
+    assert m[2] <= 1.5 * m[0]
+    assert max(err[2]) <= eps
