@@ -228,9 +228,10 @@ es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int3
  * first l(k) steps (sqrt(c)-walks afterwards); M(k) counts those meeting
  * after step l(k) without meeting before:
  *   D^(k,k) = (1 - sum_{l <= l(k)} Z_l(k)) - c^l(k) M(k) / R'(k).
- * l(k) is the largest level whose deterministic work E_l(k) (in-walks of
- * length <= l from v_k) stays within 2 R(k) / sqrt(c); at most min(3, L) for
- * the query source u and 1 for every other node.  R'(k) = R(k)
+ * l(k) is the largest level whose deterministic work (in-walks of length
+ * <= l from v_k, those of length 3 counted four times for their GPU cost)
+ * stays within 2 R(k) / sqrt(c); at most min(3, L) for the query source u
+ * and 1 for every other node.  R'(k) = R(k)
  * (ES_LDE_AS_PRINTED, smaller variance) or ceil(R(k) c^l(k)) (ES_LDE_REDUCED:
  * every pair weighs at most 1/R(k) and has Bernoulli variance at most 1/4,
  * so the Bernstein bound of Theorem 1 holds as for R(k) plain pairs). */

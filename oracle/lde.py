@@ -21,10 +21,14 @@ met before has probability c^-l(k) sum_{l > l(k)} Z_l(k), so
 over R'(k) such pairs of which M(k) meet after step l(k).
 
 Readings (the loop nesting of Algorithm 3 is garbled in the text):
-  * l(k) is the largest l <= l_max(k) whose deterministic work
-    E_l(k) = sum_{m=1}^{l} (number of length-m in-walks from v_k) stays
-    within the algorithm's bound 2 R(k) / sqrt(c); l(k) = 0 (plain
-    Algorithm 2) when even E_1(k) = d_in(k) exceeds it or R(k) = 0.
+  * l(k) is the largest l <= l_max(k) whose deterministic work stays within
+    the algorithm's bound 2 R(k) / sqrt(c); l(k) = 0 (plain Algorithm 2)
+    when even level 1 exceeds it or R(k) = 0.  The work W_l(k) counts the
+    in-walks of length <= l from v_k, E_l(k) = sum_{m <= l} (number of
+    length-m in-walks); the third level's walks are charged
+    LEVEL3_PATH_COST each, W_3 = E_2 + 4 (E_3 - E_2): on the GPU each of them
+    is two atomic passes over a node-sized array, measured at about four
+    walk steps.
     l_max is 3 for the query source, whose pairs dominate the budget, and 1
     for every other node (Z_1(k) = c / d_in(k) is a closed form).
   * R'(k) = R(k) as printed ("as_printed"), or R'(k) = ceil(R(k) c^l(k))
@@ -42,6 +46,8 @@ import scipy.sparse as sp
 
 MAX_SOURCE_LEVEL = 3
 MODE_OFF, MODE_AS_PRINTED, MODE_REDUCED = 0, 1, 2
+# work charged per three-step in-walk of the source's third exact level
+LEVEL3_PATH_COST = 4
 
 
 def transition_rows(g, rows, m: int) -> sp.csr_matrix:
@@ -97,10 +103,10 @@ def edge_costs(g, k: int) -> tuple[int, int, int]:
     """(E_1, E_2, E_3): edges traversed by the deterministic part up to
     levels 1, 2, 3 (in-walks of length 1, 2, 3 from v_k, cumulated)."""
     din = g.din
-    nb = g.in_neighbours(k)
+    nb = g.in_idx[g.in_off[k]:g.in_off[k + 1]]
     e1 = int(len(nb))
     e2 = e1 + int(din[nb].sum())
-    e3 = e2 + sum(int(din[g.in_neighbours(a)].sum()) for a in nb)
+    e3 = e2 + sum(int(din[g.in_idx[g.in_off[a]:g.in_off[a + 1]]].sum()) for a in nb)
     return e1, e2, e3
 
 
@@ -112,8 +118,11 @@ def c_power(c: float, l: int) -> float:
     return p
 
 
-def plan(g, u: int, Rk: np.ndarray, c: float, mode: int, source_max: int = MAX_SOURCE_LEVEL):
-    """(l(k) int32[n], sum_{l<=l(k)} Z_l(k) float64[n], R'(k) uint64[n])."""
+def plan(g, u: int, Rk: np.ndarray, c: float, mode: int, source_max: int = MAX_SOURCE_LEVEL,
+         source_zsum: bool = True):
+    """(l(k) int32[n], sum_{l<=l(k)} Z_l(k) float64[n], R'(k) uint64[n]).
+    source_zsum=False leaves the source's sum as NaN (for graphs where
+    Lemma 4 on the CPU is out of reach)."""
     n = g.n
     Rk = np.asarray(Rk, dtype=np.uint64)
     ell = np.zeros(n, dtype=np.int32)
@@ -127,13 +136,17 @@ def plan(g, u: int, Rk: np.ndarray, c: float, mode: int, source_max: int = MAX_S
     has = take & (g.din > 0)
     zsum[has] = c / g.din[has].astype(np.float64)
     if Rk[u] > 0:
-        costs = edge_costs(g, u)
+        e1, e2, e3 = edge_costs(g, u)
+        work = (float(e1), float(e2), float(e2) + float(LEVEL3_PATH_COST) * float(e3 - e2))
         lu = 0
         for l in range(1, source_max + 1):
-            if float(costs[l - 1]) <= budget[u]:
+            if work[l - 1] <= budget[u]:
                 lu = l
         ell[u] = lu
-        zsum[u] = float(first_meeting(g, u, c, lu)[1:].sum()) if lu > 0 else 0.0
+        if not source_zsum:
+            zsum[u] = np.nan
+        else:
+            zsum[u] = float(first_meeting(g, u, c, lu)[1:].sum()) if lu > 0 else 0.0
     if mode == MODE_REDUCED:
         cl = np.array([c_power(c, l) for l in range(source_max + 1)])
         R2 = np.ceil(Rk.astype(np.float64) * cl[ell]).astype(np.uint64)

@@ -22,8 +22,8 @@
 // accumulated in 2^-62 fixed point (exact integer sums) and squared in fixed
 // point.  The source takes l(u) <= 3 levels, every other node l(k) <= 1
 // (Z_1 is a closed form), each as far as the edge budget of Algorithm 3
-// allows: the deterministic work E_l(k) (in-walks of length <= l from v_k)
-// must stay within 2 R(k) / sqrt(c).
+// allows: the deterministic work (in-walks of length <= l from v_k, those of
+// length 3 charged kLevel3PathCost each) must stay within 2 R(k) / sqrt(c).
 //
 // Reductions run over fixed grids in a fixed order, so every result is
 // reproducible bit for bit.
@@ -38,6 +38,10 @@ namespace {
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 512;   // fixed grid of the level reductions
 constexpr int kMaxSourceLevel = 3;
+// work charged per three-step in-walk of the source's third level: each one
+// is two atomic passes over a node-sized array, measured at about four walk
+// steps on MI355X
+constexpr double kLevel3PathCost = 4.0;
 
 // Small per-query record on the device (host reads the first part).
 struct LdeSource {
@@ -338,8 +342,10 @@ es_status launch_lde(es_ctx* ctx, const es_graph* g, int32_t u, const double* lv
     // the largest l <= min(3, L) whose work E_l(u) fits 2 R(u) / sqrt(c)
     if (h.Ru > 0) {
       const double budget = (2.0 * (double)h.Ru) / sc;
+      const double work[3] = {(double)h.E[0], (double)h.E[1],
+                              (double)h.E[1] + kLevel3PathCost * (double)(h.E[2] - h.E[1])};
       for (int l = 1; l <= std::min(kMaxSourceLevel, (int)L); ++l)
-        if ((double)h.E[l - 1] <= budget) lu = l;
+        if (work[l - 1] <= budget) lu = l;
     }
     if (lu >= 2) {
       const double* lv3 = lu >= 3 ? lv + 3 * (size_t)n : nullptr;
