@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--ref-factor", type=float, default=16.0,
                    help="rmat42m: budget multiple of the pi^2 reference run that errors are measured against")
     p.add_argument("--hip-graph", type=int, default=1)
+    p.add_argument("--no-lde", action="store_true",
+                   help="skip the Algorithm 3 (local deterministic exploitation) lines")
     return p.parse_args()
 
 
@@ -253,35 +255,37 @@ def learned_main(args):
     idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
     val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
 
-    def query(u, alloc, seed, r_scale, out):
-        st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc), out)
+    def query(u, alloc, seed, r_scale, out, lde=0):
+        st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc, lde=lde), out)
         es.es_topk(ctx, out, g.n, u, args.topk, idx, val)
         return st
 
     timed = {}
-    for name, alloc in (("pi2", es.ES_ALLOC_PI2), ("learned", es.ES_ALLOC_LEARNED)):
+    variants = (("pi2", es.ES_ALLOC_PI2, 0), ("learned", es.ES_ALLOC_LEARNED, 0),
+                ("pi2_lde_reduced", es.ES_ALLOC_PI2, es.ES_LDE_REDUCED))
+    for name, alloc, lde in variants:
         for i in range(args.warmup):
-            query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s)
+            query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde)
         torch.cuda.synchronize()
         stats = []
         t = time.perf_counter()
         for i in range(args.steps):
-            stats.append(query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s))
+            stats.append(query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde))
             torch.cuda.synchronize()
             log(f"# {name} step {i}: pairs={stats[-1].pairs} walk {stats[-1].ms_walk:.1f} ms")
         timed[name] = (time.perf_counter() - t, stats)
     # accuracy at equal total pairs against a larger-budget pi^2 run
     ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
-    acc = {"pi2": [], "learned": []}
-    pairs = {"pi2": 0, "learned": 0}
+    acc = {name: [] for name, _, _ in variants}
+    pairs = {name: 0 for name, _, _ in variants}
     for u in sources[:4]:
         query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
         for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
-            for name, alloc in (("pi2", es.ES_ALLOC_PI2), ("learned", es.ES_ALLOC_LEARNED)):
-                st = query(u, alloc, seed, args.r_scale, s)
+            for name, alloc, lde in variants:
+                st = query(u, alloc, seed, args.r_scale, s, lde)
                 acc[name].append(float((s - ref).abs().max()))
                 pairs[name] += st.pairs
-        log(f"# accuracy u={u}: pi2 {acc['pi2'][-2:]} learned {acc['learned'][-2:]}")
+        log(f"# accuracy u={u}: " + " ".join(f"{k} {v[-2:]}" for k, v in acc.items()))
     L = timed["pi2"][1][0].L
     fwd_bytes = L * (4.0 * g.m + 28.0 * g.n)
     back_bytes = L * (4.0 * g.m + 44.0 * g.n)
@@ -299,7 +303,7 @@ def learned_main(args):
             "ms_backward": float(np.mean([x.ms_backward for x in st])),
         }
 
-    pl, pp = summary("learned"), summary("pi2")
+    pl, pp, pr = summary("learned"), summary("pi2"), summary("pi2_lde_reduced")
     el = timed["learned"][0]
     out = {
         "metric": "exact single-source SimRank queries/s at eps=1e-6 (learned walk budget)",
@@ -312,6 +316,7 @@ def learned_main(args):
                    "r_scale": args.r_scale, "topk": args.topk, "alloc": "learned"},
         "learned": pl,
         "pi2": pp,
+        "pi2_lde_reduced": pr,
         "roofline_spmv": {
             "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
             "achieved": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -323,8 +328,11 @@ def learned_main(args):
             "sources": sources[:4], "seeds": [wl.seed_walk + 1, wl.seed_walk + 2],
             "v_floor_ratio": es.ES_LEARNED_FLOOR,
             "max_error_pi2": acc["pi2"], "max_error_learned": acc["learned"],
+            "max_error_pi2_lde_reduced": acc["pi2_lde_reduced"],
             "mean_ratio_pi2_over_learned": float(np.mean(acc["pi2"]) / np.mean(acc["learned"])),
+            "mean_ratio_pi2_over_lde_reduced": float(np.mean(acc["pi2"]) / np.mean(acc["pi2_lde_reduced"])),
             "pairs_pi2": int(pairs["pi2"]), "pairs_learned": int(pairs["learned"]),
+            "pairs_lde_reduced": int(pairs["pi2_lde_reduced"]),
         },
         "projected_full_budget_s_per_query": float(pl["pairs_per_query_mean"] / args.r_scale / pl["walk_pairs_per_s"]),
     }
@@ -359,9 +367,9 @@ def main():
     idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
     val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
 
-    def step(i):
+    def step(i, lde=0):
         u = int(sources[i % len(sources)])
-        opts = es.make_opts(c, eps, wl.seed_walk, args.r_scale)
+        opts = es.make_opts(c, eps, wl.seed_walk, args.r_scale, lde=lde)
         st = es.es_single_source(ctx, g, u, opts, s)
         es.es_topk(ctx, s, g.n, u, args.topk, idx, val)
         return st
@@ -380,6 +388,27 @@ def main():
         log(f"# step {i}: u={int(sources[i % len(sources)])} {per_query[-1] * 1e3:.1f} ms pairs={st.pairs}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # the same queries under Algorithm 3 (local deterministic exploitation)
+    lde_out = {}
+    if not args.no_lde:
+        for name, mode in (("as_printed", es.ES_LDE_AS_PRINTED), ("reduced", es.ES_LDE_REDUCED)):
+            step(0, mode)
+            torch.cuda.synchronize()
+            lst = []
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                lst.append(step(i, mode))
+                torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            lde_out[name] = {
+                "queries_per_s": args.steps / el,
+                "pairs_per_query_mean": float(np.mean([x.pairs for x in lst])),
+                "source_levels": [int(x.lde_source_level) for x in lst],
+                "ms_budget_and_exact_levels": float(np.mean([x.ms_budget for x in lst])),
+                "ms_walk": float(np.mean([x.ms_walk for x in lst])),
+            }
+            log(f"# lde {name}: {lde_out[name]['queries_per_s']:.3f} queries/s, "
+                f"{lde_out[name]['pairs_per_query_mean']:.3g} pairs/query")
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
@@ -438,6 +467,8 @@ def main():
         "per_query_ms": [round(x * 1e3, 3) for x in per_query],
         "projected_full_budget_s_per_query": proj_s,
     }
+    if lde_out:
+        out["lde"] = lde_out
     if not args.no_cpu_baseline:
         log("# cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, src, dst, int(sources[0]), args.r_scale, args.cpu_sample_pairs)

@@ -229,9 +229,9 @@ es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int3
  * after step l(k) without meeting before:
  *   D^(k,k) = (1 - sum_{l <= l(k)} Z_l(k)) - c^l(k) M(k) / R'(k).
  * l(k) is the largest level whose deterministic work (in-walks of length
- * <= l from v_k, those of length 3 counted four times for their GPU cost)
- * stays within 2 R(k) / sqrt(c); at most min(3, L) for the query source u
- * and 1 for every other node.  R'(k) = R(k)
+ * <= l from v_k, those of length 3 charged at their GPU cost: 2 walk steps
+ * each if 8n bytes fit in 128 MiB, else 24) stays within 2 R(k) / sqrt(c);
+ * at most min(3, L) for the query source u and 1 for every other node.  R'(k) = R(k)
  * (ES_LDE_AS_PRINTED, smaller variance) or ceil(R(k) c^l(k)) (ES_LDE_REDUCED:
  * every pair weighs at most 1/R(k) and has Bernoulli variance at most 1/4,
  * so the Bernstein bound of Theorem 1 holds as for R(k) plain pairs). */

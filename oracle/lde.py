@@ -25,10 +25,10 @@ Readings (the loop nesting of Algorithm 3 is garbled in the text):
     the algorithm's bound 2 R(k) / sqrt(c); l(k) = 0 (plain Algorithm 2)
     when even level 1 exceeds it or R(k) = 0.  The work W_l(k) counts the
     in-walks of length <= l from v_k, E_l(k) = sum_{m <= l} (number of
-    length-m in-walks); the third level's walks are charged
-    LEVEL3_PATH_COST each, W_3 = E_2 + 4 (E_3 - E_2): on the GPU each of them
-    is two atomic passes over a node-sized array, measured at about four
-    walk steps.
+    length-m in-walks); the third level's walks are charged at their GPU
+    cost, W_3 = E_2 + level3_path_cost(n) (E_3 - E_2): each of them is two
+    atomic updates of a node-sized array, about 2 walk steps when that
+    array stays in cache and 24 when its updates go to HBM.
     l_max is 3 for the query source, whose pairs dominate the budget, and 1
     for every other node (Z_1(k) = c / d_in(k) is a closed form).
   * R'(k) = R(k) as printed ("as_printed"), or R'(k) = ceil(R(k) c^l(k))
@@ -46,8 +46,13 @@ import scipy.sparse as sp
 
 MAX_SOURCE_LEVEL = 3
 MODE_OFF, MODE_AS_PRINTED, MODE_REDUCED = 0, 1, 2
-# work charged per three-step in-walk of the source's third exact level
-LEVEL3_PATH_COST = 4
+
+
+def level3_path_cost(n: int) -> int:
+    """Work charged per three-step in-walk of the source's third exact level:
+    2 walk steps when the node-sized accumulator (8n bytes) fits in 128 MiB
+    of cache, 24 when it does not (measured on MI355X)."""
+    return 2 if 8 * n <= 1 << 27 else 24
 
 
 def transition_rows(g, rows, m: int) -> sp.csr_matrix:
@@ -137,7 +142,7 @@ def plan(g, u: int, Rk: np.ndarray, c: float, mode: int, source_max: int = MAX_S
     zsum[has] = c / g.din[has].astype(np.float64)
     if Rk[u] > 0:
         e1, e2, e3 = edge_costs(g, u)
-        work = (float(e1), float(e2), float(e2) + float(LEVEL3_PATH_COST) * float(e3 - e2))
+        work = (float(e1), float(e2), float(e2) + float(level3_path_cost(n)) * float(e3 - e2))
         lu = 0
         for l in range(1, source_max + 1):
             if work[l - 1] <= budget[u]:

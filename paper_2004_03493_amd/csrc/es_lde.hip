@@ -23,7 +23,7 @@
 // point.  The source takes l(u) <= 3 levels, every other node l(k) <= 1
 // (Z_1 is a closed form), each as far as the edge budget of Algorithm 3
 // allows: the deterministic work (in-walks of length <= l from v_k, those of
-// length 3 charged kLevel3PathCost each) must stay within 2 R(k) / sqrt(c).
+// length 3 charged at their GPU cost) must stay within 2 R(k) / sqrt(c).
 //
 // Reductions run over fixed grids in a fixed order, so every result is
 // reproducible bit for bit.
@@ -38,10 +38,11 @@ namespace {
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 512;   // fixed grid of the level reductions
 constexpr int kMaxSourceLevel = 3;
-// work charged per three-step in-walk of the source's third level: each one
-// is two atomic passes over a node-sized array, measured at about four walk
-// steps on MI355X
-constexpr double kLevel3PathCost = 4.0;
+// Work charged per three-step in-walk of the source's third level, in walk
+// steps: each one is two atomic updates of a node-sized array, measured on
+// MI355X at about 2 steps while that array (8n bytes) stays within 128 MiB
+// of the Infinity Cache and about 24 once its updates go to HBM.
+double level3_path_cost(int32_t n) { return 8.0 * (double)n <= 134217728.0 ? 2.0 : 24.0; }
 
 // Small per-query record on the device (host reads the first part).
 struct LdeSource {
@@ -343,7 +344,7 @@ es_status launch_lde(es_ctx* ctx, const es_graph* g, int32_t u, const double* lv
     if (h.Ru > 0) {
       const double budget = (2.0 * (double)h.Ru) / sc;
       const double work[3] = {(double)h.E[0], (double)h.E[1],
-                              (double)h.E[1] + kLevel3PathCost * (double)(h.E[2] - h.E[1])};
+                              (double)h.E[1] + level3_path_cost(n) * (double)(h.E[2] - h.E[1])};
       for (int l = 1; l <= std::min(kMaxSourceLevel, (int)L); ++l)
         if (work[l - 1] <= budget) lu = l;
     }

@@ -10,7 +10,10 @@ R-MAT n=2^20, m=1.6e7, eps=1e-6, r_scale=1e-5 (the single-source line):
     [R(k) - CAP, R(k)), and the full launch must equal head + tail;
   - back-accumulation over all n from a seeded diagonal, within 1e-9;
     then top-500 of that result;
-  - the single query equals its five stages run one after another.
+  - the single query equals its five stages run one after another;
+  - Algorithm 3 (local deterministic exploitation): l(k), R'(k) and the
+    closed-form exact parts bitwise, non-stop walks on sampled nodes and the
+    source's last pairs, estimator values, reduced query equal to its stages.
 
 R-MAT n=4.8e6, m=6.9e7 with a block of 64 sources, and the twelve uneven
 graphs with 256 sources (the batched lines): every batched answer equals the
@@ -203,3 +206,73 @@ def test_uneven_twelve_graphs_equal_single_source(es, ctx):
         sources += [int(x) for x in s]
         goq += [gi] * len(s)
     _batch_vs_single(es, ctx, graphs, goq, sources, wl.eps, wl.c, wl.seed_walk)
+
+
+def _lde_full(es, ctx, g, og, u, c, eps, r_scale, seed, ref_pi, lv, L):
+    """Algorithm 3 at full size: plan (l(k), R'(k), closed-form sums) bitwise
+    against the oracle, non-stop walks on sampled nodes and the source's last
+    pairs, estimator values, and the reduced query equal to its stages."""
+    from oracle import lde
+    R = ox.total_samples(g.n, c, eps, r_scale)
+    Rk = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_budget(ctx, g, torch.as_tensor(ref_pi).cuda(), R, es.ES_ALLOC_PI2, True, Rk)
+    ref_R = ox.budget(ref_pi, og.din, R, True)
+    assert np.array_equal(host(Rk), ref_R)
+    others = np.arange(g.n) != u
+    plans = {}
+    for mode in (1, 2):
+        ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        zsum = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+        es.es_lde_plan(ctx, g, u, lv, L, Rk, c, mode, ell, zsum, R2)
+        r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, c, mode, source_max=min(3, L), source_zsum=False)
+        assert np.array_equal(host(ell), r_ell)
+        assert np.array_equal(host(R2), r_R2)
+        gz = host(zsum)
+        assert np.array_equal(gz[others].view(np.uint64), r_z[others].view(np.uint64))
+        assert 0.0 < gz[u] < 1.0 or r_ell[u] == 0
+        plans[mode] = (ell, zsum, R2, r_ell, r_z, r_R2)
+    ell, zsum, R2, r_ell, r_z, r_R2 = plans[2]
+    say(f"  l(u)={int(r_ell[u])} zsum(u)={host(zsum)[u]:.6g} pairs {int(r_R2.sum())} (plain {int(ref_R.sum())})")
+    M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_walk_pairs_lde(ctx, g, None, R2, ell, seed, c, M)
+    gM = host(M)
+    rng = np.random.default_rng(77)
+    pool = np.flatnonzero(others & (r_R2 > 0) & (r_R2 <= CAP))
+    light = rng.choice(pool, size=min(N_RANDOM, len(pool)), replace=False)
+    R_light = np.zeros(g.n, dtype=np.uint64)
+    R_light[light] = r_R2[light]
+    ref_M = ox.walk_counts(og, R_light, seed, c, nonstop=r_ell)
+    assert np.array_equal(gM[light], ref_M[light])
+    if r_R2[u] > CAP:
+        lo = np.zeros(g.n, dtype=np.uint64)
+        hi = np.zeros(g.n, dtype=np.uint64)
+        lo[u], hi[u] = r_R2[u] - np.uint64(CAP), r_R2[u]
+        tail = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+        head = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+        es.es_walk_pairs_lde(ctx, g, u64(lo), u64(hi), ell, seed, c, tail)
+        es.es_walk_pairs_lde(ctx, g, None, u64(lo), ell, seed, c, head)
+        assert host(tail)[u] == ox.walk_counts(og, hi, seed, c, r_begin=lo, nonstop=r_ell)[u]
+        assert host(head)[u] + host(tail)[u] == gM[u]
+    D = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_diag_lde(ctx, g, R2, M, ell, zsum, c, True, D)
+    ref_D = lde.diag_estimate(r_R2[light], ref_M[light], r_ell[light], r_z[light], c, og.din[light])
+    assert np.array_equal(host(D)[light].view(np.uint64), ref_D.view(np.uint64))
+    s_st = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_backward(ctx, g, lv, L, D, c, s_st)
+    s_q = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, lde=2), s_q)
+    assert st.pairs == int(r_R2.sum()) and st.lde_source_level == int(r_ell[u])
+    assert torch.equal(s_q, s_st)
+
+
+def test_rmat1m_local_exploitation(es, ctx, rmat1m):
+    wl, g, og, sources = rmat1m
+    u = int(sources[0])
+    L = ox.num_levels(wl.c, wl.eps)
+    lv = torch.empty((L + 1) * g.n, dtype=torch.float64, device="cuda")
+    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_forward(ctx, g, u, wl.c, L, lv, pi)
+    _, ref_pi = ox.forward_levels(og, u, wl.c, L)
+    assert np.array_equal(host(pi).view(np.uint64), ref_pi.view(np.uint64))
+    _lde_full(es, ctx, g, og, u, wl.c, wl.eps, SINGLE_R_SCALE, wl.seed_walk, ref_pi, lv, L)

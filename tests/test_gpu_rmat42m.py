@@ -219,3 +219,9 @@ def test_learned_allocation(es, ctx, big):
     say(f"learned query: {st.pairs} pairs (stages {int(host(Rk).sum())})")
     assert st.pairs == int(host(Rk).sum())
     assert torch.equal(s_q, s_st)
+
+
+def test_local_exploitation(es, ctx, big):
+    from test_gpu_fullsize import _lde_full
+    wl, g, cg, u, L = big["wl"], big["g"], big["cg"], big["u"], big["L"]
+    _lde_full(es, ctx, g, cg, u, wl.c, wl.eps, R_SCALE, wl.seed_walk, big["ref_pi"], big["lv"], L)

@@ -147,7 +147,7 @@ def test_plan_rule():
     assert np.all(g.din[others & (Rk > 0) & (ell == 0)] > budget[others & (Rk > 0) & (ell == 0)])
     assert np.all(zsum[one] == C / g.din[one].astype(np.float64))
     e = lde.edge_costs(g, u)
-    work = (e[0], e[1], e[1] + lde.LEVEL3_PATH_COST * (e[2] - e[1]))
+    work = (e[0], e[1], e[1] + lde.level3_path_cost(n) * (e[2] - e[1]))
     assert ell[u] == max(l for l in (0, 1, 2, 3) if l == 0 or work[l - 1] <= budget[u])
     _, _, R2 = lde.plan(g, u, Rk, C, lde.MODE_REDUCED)
     cl = np.array([1.0, C, C * C, C * C * C])
