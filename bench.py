@@ -27,14 +27,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 compute units at 2.4 GHz, 64 lanes each; HBM3E 8 TB/s.
-CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
+# MI355X: 256 compute units at 2.4 GHz; HBM3E 8 TB/s.  The VALU retires
+# 32-bit lane operations at the fp32 vector rate, 128 lanes per CU per clock
+# (157.3 TFLOP/s = 2 x 78.6 T lane-FMAs/s); a Philox-only kernel sustains
+# 5.3e13 lane-instructions/s, above what 64 lanes per clock would allow.
+CUS, CLOCK_HZ, LANES = 256, 2.4e9, 128
 PEAK_INT_TOPS = CUS * LANES * CLOCK_HZ / 1e12       # 32-bit integer VALU lane-ops
 PEAK_HBM_GBS = 8000.0
-# 32-bit integer operations of one Philox4x64-10 block, counted from its
-# definition: 10 rounds x (two 64x64->128 products of 12 ops each [4 partial
-# products, lo and hi, plus 4 carry adds], 8 xors, 4 ops of key schedule).
-OPS_PER_PHILOX_BLOCK = 10 * (2 * 12 + 8 + 4)
+# 32-bit vector operations of one Philox4x64-10 block, counted from its
+# definition: 10 rounds x (two 64x64->128 products, each 4 partial products
+# as 32x32->64 multiply-adds plus 2 carry adds; two 64-bit outputs of two
+# xors each, 8 32-bit xors).  The key schedule is the same for every lane.
+OPS_PER_PHILOX_BLOCK = 10 * (2 * (4 + 2) + 8)
 # one joint walk step: two 64x32 multiply-high index maps (6 ops each)
 OPS_PER_WALK_STEP = 12
 
