@@ -199,3 +199,53 @@ def test_accuracy_against_power_method(es, ctx):
     assert m[1] < m[0]
     assert m[2] <= 1.5 * m[0]
     assert max(err[2]) <= eps
+
+
+def _oracle_lde_query(og, u, eps, seed, r_scale, mode):
+    L = ox.num_levels(C, eps)
+    lv, pi = ox.forward_levels(og, u, C, L)
+    R = ox.total_samples(og.n, C, eps, r_scale)
+    Rk = ox.budget(pi, og.din, R, True)
+    ell, z, R2 = lde.plan(og, u, Rk, C, mode, source_max=min(3, L))
+    M = ox.walk_counts(og, R2, seed, C, nonstop=ell)
+    return ox.back_accumulate(og, lv, lde.diag_estimate(R2, M, ell, z, C, og.din), C)
+
+
+def test_tiny_graphs_and_small_l(es, ctx):
+    """Empty and tiny graphs, sources without in-neighbours, and eps = 0.9
+    (L = 2, so the source gets at most two exact levels)."""
+    cases = [(1, [], []), (3, [], []), (2, [0], [1]), (4, [0, 0, 1], [1, 1, 1]),
+             (5, [1, 2, 3, 4, 2, 3], [0, 0, 0, 0, 1, 1]), (6, [0, 1, 2, 3, 4, 5], [1, 2, 3, 4, 5, 0])]
+    for n, src, dst in cases:
+        g = es.Graph(ctx, n, np.array(src, dtype=np.int32), np.array(dst, dtype=np.int32))
+        og = OracleGraph(n, src, dst)
+        s = torch.empty(n, dtype=torch.float64, device="cuda")
+        for u in range(n):
+            for eps in (1e-3, 0.9):
+                for mode in (1, 2):
+                    es.es_single_source(ctx, g, u, es.make_opts(C, eps, 3, 1e-2, lde=mode), s)
+                    ref = _oracle_lde_query(og, u, eps, 3, 1e-2, mode)
+                    assert np.abs(host(s) - ref).max() <= S_TOL, (n, u, eps, mode)
+
+
+def test_lde_argument_errors(es, ctx):
+    g, og = pair(es, ctx, "random_small")
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(es.EsError) as e:
+        es.es_single_source(ctx, g, 0, es.make_opts(C, 1e-3, 1, 1e-3, lde=3), s)
+    assert e.value.status == es.ES_EINVAL
+    L = ox.num_levels(C, 1e-3)
+    lv = torch.zeros((L + 1) * g.n, dtype=torch.float64, device="cuda")
+    Rk = torch.zeros(g.n, dtype=torch.uint64, device="cuda")
+    ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    z = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    for u, c, Lx, mode in ((-1, C, L, 1), (g.n, C, L, 1), (0, 1.5, L, 1), (0, C, 0, 1), (0, C, L, 5)):
+        with pytest.raises(es.EsError) as e:
+            es.es_lde_plan(ctx, g, u, lv, Lx, Rk, c, mode, ell, z, R2)
+        assert e.value.status == es.ES_EINVAL
+    # batches run Algorithm 2 only
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda")]
+    with pytest.raises(es.EsError) as e:
+        es.es_batch(ctx, [g], [0], [0], es.make_opts(C, 1e-3, 1, 1e-3, lde=1), outs)
+    assert e.value.status == es.ES_EUNSUPPORTED
