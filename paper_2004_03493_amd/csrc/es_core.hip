@@ -12,6 +12,19 @@
 
 namespace es {
 
+namespace {
+
+__global__ void walk_adj_kernel(int64_t m, const int32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
+                                WalkEntry* __restrict__ adj) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = in_idx[e];
+    const int32_t o = in_off[v];
+    adj[e] = WalkEntry{v, o, in_off[v + 1] - o, 0};
+  }
+}
+
+}  // namespace
+
 es_status fail(es_ctx* ctx, es_status st, const char* fmt, ...) {
   if (ctx) {
     char buf[512];
@@ -561,6 +574,14 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
   if (e == hipSuccess) e = up((void**)&g->dout_ext, h.dout_ext.data(), 4 * h.dout_ext.size());
   if (e == hipSuccess) e = up((void**)&g->ext_of, h.ext_of.data(), 4 * h.ext_of.size());
   if (e == hipSuccess) e = up((void**)&g->int_of, h.int_of.data(), 4 * h.int_of.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&g->walk_adj, sizeof(WalkEntry) * std::max<size_t>(1, h.in_idx.size()));
+  if (e == hipSuccess && !h.in_idx.empty()) {
+    const int64_t mm = (int64_t)h.in_idx.size();
+    const int blocks = (int)std::min<int64_t>((mm + 255) / 256, (int64_t)ctx->num_cus * 64);
+    walk_adj_kernel<<<blocks, 256>>>(mm, g->in_off, g->in_idx, g->walk_adj);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
   if (e != hipSuccess) {
     es_graph_destroy(g);
     return hip_fail(ctx, e, "graph upload");
@@ -586,6 +607,7 @@ es_status es_graph_destroy(es_graph* g) {
   (void)hipFree(g->out_idx);
   (void)hipFree(g->in_off);
   (void)hipFree(g->in_idx);
+  (void)hipFree(g->walk_adj);
   (void)hipFree(g->inv_din);
   (void)hipFree(g->din_int);
   (void)hipFree(g->din_ext);

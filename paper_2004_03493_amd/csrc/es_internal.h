@@ -50,6 +50,16 @@ struct BatchPlan;
 
 }  // namespace es
 
+// One in-CSR entry for the walks: the in-neighbour's internal id together with
+// its own row (offset into the in-CSR and in-degree), so a walk step needs one
+// dependent 16-byte load instead of two.
+struct alignas(16) WalkEntry {
+  int32_t id;
+  int32_t off;
+  int32_t deg;
+  int32_t pad;
+};
+
 // Device graph.  Nodes are stored under internal ids: the rank of the node by
 // total degree (descending, ties by id), so that the hub entries every SpMV
 // level gathers share few cache lines.  Callers only ever see external ids.
@@ -61,6 +71,7 @@ struct es_graph {
   int32_t* out_idx = nullptr;  // [m]
   int32_t* in_off = nullptr;   // [n+1]  internal rows list I(v): internal ids in ascending EXTERNAL id order
   int32_t* in_idx = nullptr;   // [m]
+  WalkEntry* walk_adj = nullptr;  // [m]  in_idx[e] with its row: (id, in_off[id], d_in(id))
   double* inv_din = nullptr;   // [n]    1/d_in(v) by internal id, 0 where d_in = 0
   int32_t* din_int = nullptr;  // [n]    d_in by internal id
   int32_t* din_ext = nullptr;  // [n]    d_in by external id

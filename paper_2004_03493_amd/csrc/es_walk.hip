@@ -279,7 +279,6 @@ __device__ __forceinline__ uint32_t mulhi_index(uint64_t w, uint32_t d) {
 
 struct WalkArgs {
   const int32_t* __restrict__ in_off;
-  const int32_t* __restrict__ in_idx;
   const int32_t* __restrict__ active;
   const uint64_t* __restrict__ prefix;
   const uint64_t* __restrict__ r_begin;
@@ -293,18 +292,25 @@ struct WalkArgs {
   int32_t B;
   uint64_t seed;
   const int32_t* __restrict__ nonstop;  // non-stop variant only: l(k) per count index
+  const WalkEntry* __restrict__ adj;    // in-CSR entries with their own rows
 };
 
-// One step of both walks; returns 1 = met, 0 = moved without meeting, -1 = a walk is stuck.
-__device__ __forceinline__ int walk_step(const int32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
-                                         int32_t& x, int32_t& y, uint64_t wx, uint64_t wy) {
-  const int32_t ox = in_off[x], ex = in_off[x + 1];
-  const int32_t oy = in_off[y], ey = in_off[y + 1];
-  const uint32_t dx = (uint32_t)(ex - ox), dy = (uint32_t)(ey - oy);
-  if (dx == 0 || dy == 0) return -1;
-  x = in_idx[ox + mulhi_index(wx, dx)];
-  y = in_idx[oy + mulhi_index(wy, dy)];
-  return x == y ? 1 : 0;
+// A walk's position: node id and its in-CSR row (offset, in-degree).
+struct Pos {
+  int32_t id, off, deg;
+};
+
+// One step of both walks; returns 1 = met, 0 = moved without meeting, -1 = a
+// walk is stuck.  Each walk reads one 16-byte entry of its current row, which
+// already holds the next node's row.
+__device__ __forceinline__ int walk_step(const WalkEntry* __restrict__ adj, Pos& x, Pos& y, uint64_t wx,
+                                         uint64_t wy) {
+  if (x.deg == 0 || y.deg == 0) return -1;
+  const WalkEntry ex = adj[x.off + mulhi_index(wx, (uint32_t)x.deg)];
+  const WalkEntry ey = adj[y.off + mulhi_index(wy, (uint32_t)y.deg)];
+  x = Pos{ex.id, ex.off, ex.deg};
+  y = Pos{ey.id, ey.off, ey.deg};
+  return x.id == y.id ? 1 : 0;
 }
 
 // Sum the per-lane work counters over the wave, one atomic each (wave-uniform call).
@@ -370,12 +376,16 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     const uint64_t iend = (i + run < total) ? i + run : total;
     int32_t p = 0;
     uint64_t pbeg = 0, pend = 0;
-    // ids of the node of slot p: count index, first sample, graph id, stream id
+    // the node of slot p: count index, first sample, and its position in the graph
     int32_t pk = 0;
     uint64_t prb = 0;
+    Pos pstart{0, 0, 0};
     auto load_node = [&]() {
       pk = a.active[p];
       prb = a.r_begin ? a.r_begin[pk] : 0ull;
+      const int32_t kg = a.to_graph ? a.to_graph[pk] : pk;
+      const int32_t o = a.in_off[kg];
+      pstart = Pos{kg, o, a.in_off[kg + 1] - o};
     };
     if (i < iend) {
       // last active slot whose prefix is <= i
@@ -391,7 +401,8 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       load_node();
     }
     bool in_pair = false;
-    int32_t k = 0, x = 0, y = 0, t = 0, T = 0, kg = 0;
+    int32_t k = 0, t = 0, T = 0;
+    Pos x{0, 0, 0}, y{0, 0, 0};
     int32_t nsl = 0;  // non-stop steps of the current pair
     uint64_t r = 0, kc = 0;
     for (;;) {
@@ -420,10 +431,9 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
             k = pk;
             r = rr;
             T = TT;
-            kg = a.to_graph ? a.to_graph[k] : k;
             kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
-            x = kg;
-            y = kg;
+            x = pstart;
+            y = pstart;
             t = 0;
             in_pair = true;
             break;
@@ -451,14 +461,14 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
         lt = lifetime(w.w0) | (lifetime(w.w1) << 16) | (lifetime(w.w2) << 32) | (lifetime(w.w3) << 48);
         continue;  // the pair starts from the cache on the next iteration
       }
-      int st = walk_step(a.in_off, a.in_idx, x, y, w.w0, w.w1);
+      int st = walk_step(a.adj, x, y, w.w0, w.w1);
       t += 1;
       ++nsteps;
       if constexpr (kNonstop) {
         if (st > 0 && t <= nsl) st = -1;  // met during the exact levels: not counted
       }
       if (st == 0 && t < T) {
-        st = walk_step(a.in_off, a.in_idx, x, y, w.w2, w.w3);
+        st = walk_step(a.adj, x, y, w.w2, w.w3);
         t += 1;
         ++nsteps;
         if constexpr (kNonstop) {
@@ -568,7 +578,6 @@ es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, co
   scan_write_kernel<<<nb, kScanThreads, 0, ctx->stream>>>(n, r_begin, r_end, bcnt, bsum, tot, active, prefix);
   WalkArgs a;
   a.in_off = g->in_off;
-  a.in_idx = g->in_idx;
   a.active = active;
   a.prefix = prefix;
   a.r_begin = r_begin;
@@ -582,6 +591,7 @@ es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, co
   a.B = B;
   a.seed = seed;
   a.nonstop = nonstop;
+  a.adj = g->walk_adj;
   const int grid = ctx->num_cus * 8;
   if (ctx->ev_walk_begin) ES_CHECK_HIP(ctx, hipEventRecord(ctx->ev_walk_begin, ctx->stream));
   if (T) walk_pairs_kernel<true, false><<<grid, kWalkThreads, 0, ctx->stream>>>(a);
