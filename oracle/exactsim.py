@@ -33,6 +33,10 @@ Readings where the text is ambiguous (each also listed in the design notes):
   integers; pi^l(i) = sqrt c * (acc * 2^-62).  The result differs from exact
   arithmetic by at most d_out(i) 2^-63 per entry and does not depend on the
   summation order.
+* Sparse linearization (Section 3.2, Lemma 2) removes the stored entries
+  pi^l(k) <= (1 - sqrt c)^2 eps_s.  The forward pass still propagates the full
+  vectors and the budget uses the full pi(k); only the copy of the levels that
+  the back-accumulation reads is sparse (``sparse_eps`` of ``query``).
 """
 from __future__ import annotations
 
@@ -235,6 +239,33 @@ def back_accumulate(g: OracleGraph, levels: np.ndarray, D: np.ndarray, c: float)
     return s
 
 
+# ---------------------------------------------------------------------------
+# Sparse linearization (Section 3.2, Lemma 2)
+# ---------------------------------------------------------------------------
+
+def sparse_threshold(c: float, eps_s: float) -> float:
+    """theta = (1 - sqrt c)^2 eps_s, the cut of sparse linearization: stored
+    entries pi^l(k) <= theta are removed, which adds at most eps_s to every
+    s(u, j) (Lemma 2) and leaves at most 1/theta entries over all levels (the
+    levels' total mass is at most 1).  Evaluated as ((1 - sc) * (1 - sc)) *
+    eps_s in float64."""
+    sc = math.sqrt(c)
+    return (1.0 - sc) * (1.0 - sc) * eps_s
+
+
+def sparsify_levels(levels: np.ndarray, theta: float) -> np.ndarray:
+    """The levels that sparse linearization keeps: every pi^l(k) <= theta set to zero.
+
+    Reading: the forward pass itself propagates the full pi^(l-1) (so every
+    kept entry is exact and each removed one is off by less than theta, the
+    per-entry error Lemma 2's proof assumes); only the stored copy that the
+    back-accumulation reads is sparse, and the sample budget uses the full
+    pi(k) of the forward pass."""
+    out = np.array(levels, dtype=np.float64, copy=True)
+    out[out <= theta] = 0.0
+    return out
+
+
 def topk(s: np.ndarray, u: int, k: int):
     """k largest s(j), j != u, ties to the smaller id."""
     idx = np.arange(len(s))
@@ -246,8 +277,11 @@ def topk(s: np.ndarray, u: int, k: int):
 
 def query(g: OracleGraph, u: int, c: float, eps: float, seed: int, r_scale: float = 1.0,
           exact_small_din: bool = True, d_override: np.ndarray | None = None, alloc: str = "pi2",
-          threads: int = 0) -> dict:
-    """One ExactSim single-source query; returns every intermediate."""
+          threads: int = 0, sparse_eps: float = 0.0) -> dict:
+    """One ExactSim single-source query; returns every intermediate.
+
+    ``sparse_eps`` > 0 runs the back-accumulation on the levels of sparse
+    linearization with threshold sparse_threshold(c, sparse_eps)."""
     L = num_levels(c, eps)
     levels, pi = forward_levels(g, u, c, L)
     R = total_samples(g.n, c, eps, r_scale)
@@ -264,5 +298,8 @@ def query(g: OracleGraph, u: int, c: float, eps: float, seed: int, r_scale: floa
             raise ValueError(alloc)
         M = walk_counts(g, Rk, seed, c, threads)
         D = diag_estimate(Rk, M, g.din, c, exact_small_din)
-    s = back_accumulate(g, levels, D, c)
-    return dict(L=L, R=R, levels=levels, pi=pi, Rk=Rk, M=M, D=D, s=s)
+    kept = levels
+    if sparse_eps > 0.0:
+        kept = sparsify_levels(levels, sparse_threshold(c, sparse_eps))
+    s = back_accumulate(g, kept, D, c)
+    return dict(L=L, R=R, levels=levels, kept=kept, pi=pi, Rk=Rk, M=M, D=D, s=s)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import test_oracle_pins as pins
+import test_oracle_sparse as sparse_pins
 from oracle import exactsim as ox
 from oracle import simrank as sr
 
@@ -81,6 +82,29 @@ def _levels_off_by_one(c, eps):
     return _orig_levels(c, eps) - 1
 
 
+def _sparsify_strict(levels, theta):
+    out = np.array(levels, dtype=np.float64, copy=True)
+    out[out < theta] = 0.0  # keeps entries equal to theta
+    return out
+
+
+def _sparsify_inverted(levels, theta):
+    out = np.array(levels, dtype=np.float64, copy=True)
+    out[out > theta] = 0.0  # removes the large entries
+    return out
+
+
+def _threshold_not_squared(c, eps_s):
+    return (1.0 - math.sqrt(c)) * eps_s
+
+
+def _sparsify_shifted(levels, theta):
+    out = np.array(levels, dtype=np.float64, copy=True)
+    mask = out <= theta
+    out[np.roll(mask, 1, axis=0)] = 0.0  # the mask of level l applied to level l + 1
+    return out
+
+
 _orig_forward = ox.forward_levels
 _orig_diag = ox.diag_estimate
 _orig_exact_diag = sr.exact_diagonal
@@ -105,6 +129,14 @@ MUTANTS = [
      [pins.test_exact_diagonal_special_cases]),
     ("levels_one_short", ox, "num_levels", _levels_off_by_one,
      [pins.test_levels_at_paper_settings]),
+    ("sparsify_keeps_equal", ox, "sparsify_levels", _sparsify_strict,
+     [sparse_pins.test_entry_at_threshold_is_removed]),
+    ("sparsify_inverted", ox, "sparsify_levels", _sparsify_inverted,
+     [sparse_pins.test_cycle_closed_form, lambda: sparse_pins.test_lemma2_error_bound(0)]),
+    ("threshold_not_squared", ox, "sparse_threshold", _threshold_not_squared,
+     [sparse_pins.test_cycle_closed_form, sparse_pins.test_threshold_value]),
+    ("sparsify_shifted_level", ox, "sparsify_levels", _sparsify_shifted,
+     [sparse_pins.test_removed_mass_through_ppr_pairs]),
 ]
 
 
