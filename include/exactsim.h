@@ -88,6 +88,10 @@ typedef struct {
                                 ES_LEARNED_FLOOR = 1/2 recommended, 0 = none)              */
   int32_t lde;               /* local deterministic exploitation (Algorithm 3; below):
                                 ES_LDE_OFF, ES_LDE_AS_PRINTED or ES_LDE_REDUCED            */
+  double sparse_eps;         /* sparse linearization (Section 3.2, Lemma 2): 0 keeps the
+                                levels dense; in (0, 1) the back-accumulation reads only
+                                the entries pi^l(k) > (1-sqrt c)^2 sparse_eps, which
+                                lowers s(u, j) by at most sparse_eps (es_forward_sparse) */
 } es_query_opts;
 
 typedef enum {
@@ -114,6 +118,10 @@ typedef struct {
   float ms_backward;         /*   back-accumulation                                  */
   int32_t lde_source_level;  /* l(u) of the source under Algorithm 3 (0 when off)    */
   double lde_source_zsum;    /* sum_{l <= l(u)} Z_l(u), the source's exact part      */
+  uint64_t level_entries;    /* pi^l entries stored for the back-accumulation:      */
+                             /*   (L+1) n dense, the kept ones with sparse_eps > 0  */
+  uint64_t level_bytes;      /* device bytes holding the levels: 8 (L+1) n dense;   */
+                             /*   12 per kept entry plus the dense working slots    */
 } es_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -167,6 +175,25 @@ es_status es_total_samples(int32_t n, double c, double eps, double r_scale, doub
 es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
                      double* pi);
 
+/* Sparse linearization (Section 3.2, Lemma 2).  Runs Algorithm 1, lines 2-5
+ * exactly as es_forward (same pi^l, same pi) but stores only the entries
+ * pi^l(k) > theta = ((1-sqrt c)*(1-sqrt c))*sparse_eps (float64, in that
+ * order): idx (device int32 [cap], node ids) and val (device float64 [cap],
+ * pi^l(k)) receive the kept entries of level 0, then of level 1, ..., then of
+ * level L, in no particular order within a level (each node at most once per
+ * level); counts (host uint64 [L+1]) receives the number per level and pi
+ * (device float64 [n], nullable) the full pi.  The levels' mass is at most 1,
+ * so at most 1/theta entries are kept; es_sparse_capacity gives a cap that
+ * always suffices.  Synchronizes the stream.  Errors: ES_EINVAL (as
+ * es_forward; sparse_eps outside (0, 1); cap < 0; a NULL list with cap > 0),
+ * ES_EOVERFLOW (more than cap entries: the lists hold the first cap). */
+es_status es_forward_sparse(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double sparse_eps,
+                            int64_t cap, int32_t* idx, double* val, uint64_t* counts, double* pi);
+/* *cap = min((L+1) n, floor((1 + (L+1)(m+n) 2^-62)/theta) + 1): the kept entries
+ * exceed theta and sum to at most the levels' mass, 1 plus the forward pass's
+ * rounding.  Errors: ES_EINVAL (negative sizes, c or sparse_eps out of range). */
+es_status es_sparse_capacity(int32_t n, int64_t m, int32_t L, double c, double sparse_eps, int64_t* cap);
+
 /* Algorithm 1, lines 6-8 and Section 3.2.  Rk: device uint64 [n] receives
  * R(k) = ceil(R * (pi(k)*pi(k))) (ES_ALLOC_PI2) or ceil(R * pi(k))
  * (ES_ALLOC_PI); 0 where pi(k) = 0 and, with exact_small_din, where
@@ -208,8 +235,13 @@ es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int3
 
 /* Whole query: every step above with library-owned workspaces.
  * s_out: device float64 [n].  stats (host, nullable) is filled after a
- * stream synchronization.  Errors: as the steps, plus ES_EINVAL for
- * r_scale <= 0 or eps outside (0, 1). */
+ * stream synchronization.  With opts->sparse_eps > 0 the forward pass keeps
+ * the levels as es_forward_sparse does (Algorithm 3 still reads levels
+ * 0..min(3, L) densely), the sample budget uses the full pi, and
+ * s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i), plus
+ * D(j) pi^(L-l)(j)/(1-sqrt c) where pi^(L-l)(j) is kept.  Errors: as the
+ * steps, plus ES_EINVAL for r_scale <= 0, eps outside (0, 1) or sparse_eps
+ * outside [0, 1). */
 es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_query_opts* opts,
                            double* s_out, es_stats* stats);
 

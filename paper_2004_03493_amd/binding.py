@@ -39,6 +39,7 @@ SYMBOLS = (
     "es_backward", "es_single_source", "es_topk", "es_batch", "es_batch_tuning",
     "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
     "es_budget_weighted", "es_lde_plan", "es_walk_pairs_lde", "es_diag_lde",
+    "es_forward_sparse", "es_sparse_capacity",
 )
 
 
@@ -51,7 +52,8 @@ class EsError(RuntimeError):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("r_scale", ctypes.c_double), ("alloc", ctypes.c_int32), ("exact_small_din", ctypes.c_int32),
-                ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double), ("lde", ctypes.c_int32)]
+                ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double), ("lde", ctypes.c_int32),
+                ("sparse_eps", ctypes.c_double)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -66,7 +68,8 @@ class Stats(ctypes.Structure):
                 ("walk_steps", ctypes.c_uint64), ("ms_forward", ctypes.c_float),
                 ("ms_budget", ctypes.c_float), ("ms_walk", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("ms_backward", ctypes.c_float), ("lde_source_level", ctypes.c_int32),
-                ("lde_source_zsum", ctypes.c_double)]
+                ("lde_source_zsum", ctypes.c_double), ("level_entries", ctypes.c_uint64),
+                ("level_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -98,6 +101,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_num_levels": [dbl, dbl, ctypes.POINTER(i32)],
         "es_total_samples": [i32, dbl, dbl, dbl, ctypes.POINTER(dbl)],
         "es_forward": [P, P, i32, dbl, i32, P, P],
+        "es_forward_sparse": [P, P, i32, dbl, i32, dbl, i64, P, P, ctypes.POINTER(u64), P],
+        "es_sparse_capacity": [i32, i64, i32, dbl, dbl, ctypes.POINTER(i64)],
         "es_budget": [P, P, P, dbl, i32, i32, P, ctypes.POINTER(u64)],
         "es_walk_pairs": [P, P, P, P, u64, dbl, P],
         "es_diag": [P, P, P, P, dbl, i32, P],
@@ -240,6 +245,22 @@ def es_forward(ctx: Context, g: Graph, u: int, c: float, L: int, levels, pi):
                                      _ptr(pi, torch.float64, g.n, "pi")), ctx)
 
 
+def es_sparse_capacity(n: int, m: int, L: int, c: float, sparse_eps: float) -> int:
+    cap = ctypes.c_int64()
+    _check(load_library().es_sparse_capacity(n, m, L, c, sparse_eps, ctypes.byref(cap)))
+    return cap.value
+
+
+def es_forward_sparse(ctx: Context, g: Graph, u: int, c: float, L: int, sparse_eps: float, idx, val, pi=None):
+    """Kept entries of the levels (sparse linearization); returns the count per level."""
+    cap = min(idx.numel(), val.numel())
+    counts = (ctypes.c_uint64 * (L + 1))()
+    _check(load_library().es_forward_sparse(ctx.handle, g.handle, u, c, L, sparse_eps, cap,
+                                            _ptr(idx, torch.int32, cap, "idx"), _ptr(val, torch.float64, cap, "val"),
+                                            counts, _ptr(pi, torch.float64, g.n, "pi")), ctx)
+    return [int(x) for x in counts]
+
+
 def es_budget(ctx: Context, g: Graph, pi, R: float, alloc: int, exact_small_din: bool, Rk,
               want_total: bool = False):
     tot = ctypes.c_uint64()
@@ -269,13 +290,14 @@ def es_backward(ctx: Context, g: Graph, levels, L: int, D, c: float, s):
 
 def make_opts(c: float, eps: float, seed: int, r_scale: float = 1.0, alloc: int = ES_ALLOC_PI2,
               exact_small_din: bool = True, d_override=None, v_floor_ratio: float = ES_LEARNED_FLOOR,
-              lde: int = ES_LDE_OFF) -> QueryOpts:
+              lde: int = ES_LDE_OFF, sparse_eps: float = 0.0) -> QueryOpts:
     o = QueryOpts()
     o.c, o.eps, o.seed, o.r_scale = c, eps, seed, r_scale
     o.alloc, o.exact_small_din = alloc, int(exact_small_din)
     o.d_override = None if d_override is None else d_override.data_ptr()
     o.v_floor_ratio = v_floor_ratio
     o.lde = lde
+    o.sparse_eps = sparse_eps
     return o
 
 

@@ -714,6 +714,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI)
     return fail(ctx, o->alloc == ES_ALLOC_LEARNED ? ES_EUNSUPPORTED : ES_EINVAL, "allocation %d", o->alloc);
   if (o->lde != 0) return fail(ctx, ES_EUNSUPPORTED, "batches run Algorithm 2 only (lde = 0)");
+  if (o->sparse_eps != 0.0) return fail(ctx, ES_EUNSUPPORTED, "batches keep dense levels (sparse_eps = 0)");
   es_batch_opts defaults{0, 1, 0, 0};
   const es_batch_opts& b = bo ? *bo : defaults;
   if (b.force_width && (b.force_width < 8 || b.force_width > 64 || (b.force_width & (b.force_width - 1))))

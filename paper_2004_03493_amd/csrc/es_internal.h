@@ -150,6 +150,9 @@ enum Slot : int {
   kWsLdeMisc,
   kWsLdeLv,
   kWsLdeRin,
+  kWsSpIdx,
+  kWsSpVal,
+  kWsSpCnt,
   kWsCount
 };
 
@@ -171,9 +174,30 @@ void* workspace(es_ctx* ctx, int slot, size_t bytes, es_status* st);
 // lifetime threshold table for decay c, cached on the context
 es_status lifetime_table(es_ctx* ctx, double c);
 
+// Sparse linearization (Section 3.2, Lemma 2): the stored levels keep only the
+// entries pi^l(k) > theta, in one list of (internal id, value) for all levels;
+// level l's entries follow those of levels < l, in no particular order within
+// the level.  cnt[l] counts level l's entries and cnt[L + 1] all of them; the
+// list holds at most cap entries (more cannot occur: see sparse_capacity).
+struct SparseLevels {
+  double theta;
+  int32_t nkeep;             // levels 0..nkeep-1 also stay dense in their slots
+  int32_t* idx;              // device [cap]
+  double* val;               // device [cap]
+  unsigned long long* cnt;   // device [L + 2]
+  uint64_t cap;
+};
+// An upper bound on the entries above theta over levels 0..L: their mass is at most 1.
+uint64_t sparse_capacity(int32_t n, int64_t m, int32_t L, double theta);
+// internal -> external ids over the whole list
+es_status launch_sparse_ids(es_ctx* ctx, const es_graph* g, int32_t L, const SparseLevels& sp);
+
 // launchers (enqueue on ctx->stream)
+// Forward levels.  sp == NULL: levels holds L + 1 dense slots (pi^l in slot l).
+// sp != NULL: levels holds sp->nkeep + 1 dense slots (pi^l in slot min(l, nkeep))
+// and the kept entries go to sp.
 es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
-                         double* pi, int64_t* q0, int64_t* q1);
+                         double* pi, int64_t* q0, int64_t* q1, const SparseLevels* sp = nullptr);
 es_status launch_budget(es_ctx* ctx, const es_graph* g, const double* pi, const int32_t* din, double R,
                         int32_t alloc, int32_t exact_small_din, const float* vhat, double vbar_inv, uint64_t* Rk);
 // Walk pairs over sample counts indexed by internal ids (external_counts = false)
@@ -207,8 +231,10 @@ es_status launch_diag_lde(es_ctx* ctx, int32_t n, const uint64_t* Rk, const uint
                           const double* zsum, const int32_t* din, double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1
 es_status launch_permute_f64(es_ctx* ctx, int32_t n, int32_t rows, const double* src, const int32_t* map, double* dst);
+// Back-accumulation from the dense levels (sp == NULL, levels [L + 1][n]) or
+// from the stored entries of sparse linearization (levels unused).
 es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,
-                          double c, double* s, double* s_tmp);
+                          double c, double* s, double* s_tmp, const SparseLevels* sp = nullptr);
 es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                       double* val_out);
 es_status build_plan(es_ctx* ctx, const int32_t* off_host, int32_t n, SpmvPlan* plan);

@@ -1,4 +1,5 @@
 // Public entry points for the steps of a query and the whole query.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -65,6 +66,50 @@ es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_
   ES_TRY(launch_forward(ctx, g, g->h_int_of[u], c, L, lv, pii, q0, q1));
   ES_TRY(launch_permute_f64(ctx, n, L + 1, lv, g->int_of, levels));
   return launch_permute_f64(ctx, n, 1, pii, g->int_of, pi);
+}
+
+es_status es_sparse_capacity(int32_t n, int64_t m, int32_t L, double c, double sparse_eps, int64_t* cap) {
+  if (!cap || n < 0 || m < 0 || L < 0) return ES_EINVAL;
+  if (!valid_c(c) || !(sparse_eps > 0.0 && sparse_eps < 1.0)) return ES_EINVAL;
+  const double sc = std::sqrt(c);
+  *cap = (int64_t)sparse_capacity(n, m, L, (1.0 - sc) * (1.0 - sc) * sparse_eps);
+  return ES_OK;
+}
+
+es_status es_forward_sparse(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double sparse_eps,
+                            int64_t cap, int32_t* idx, double* val, uint64_t* counts, double* pi) {
+  if (!ctx || !g) return ES_EINVAL;
+  if (u < 0 || u >= g->n) return fail(ctx, ES_EINVAL, "source %d outside [0, %d)", u, g->n);
+  if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
+  if (L < 0 || !counts) return fail(ctx, ES_EINVAL, "bad L or null counts");
+  if (!(sparse_eps > 0.0 && sparse_eps < 1.0)) return fail(ctx, ES_EINVAL, "sparse_eps=%g outside (0, 1)", sparse_eps);
+  if (cap < 0 || (cap > 0 && (!idx || !val))) return fail(ctx, ES_EINVAL, "bad capacity or null list");
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  es_status st;
+  const int32_t n = g->n;
+  auto* q0 = (int64_t*)workspace(ctx, kWsQ0, sizeof(int64_t) * (size_t)n, &st);
+  if (!q0) return st;
+  auto* q1 = (int64_t*)workspace(ctx, kWsQ1, sizeof(int64_t) * (size_t)n, &st);
+  if (!q1) return st;
+  auto* lv = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)n, &st);
+  if (!lv) return st;
+  auto* pii = (double*)workspace(ctx, kWsPi, sizeof(double) * (size_t)n, &st);
+  if (!pii) return st;
+  auto* cnt = (unsigned long long*)workspace(ctx, kWsSpCnt, sizeof(uint64_t) * (size_t)(L + 2), &st);
+  if (!cnt) return st;
+  const double sc = std::sqrt(c);
+  SparseLevels sp{(1.0 - sc) * (1.0 - sc) * sparse_eps, 0, idx, val, cnt, (uint64_t)cap};
+  ES_TRY(launch_forward(ctx, g, g->h_int_of[u], c, L, lv, pii, q0, q1, &sp));
+  ES_TRY(launch_sparse_ids(ctx, g, L, sp));
+  if (pi) ES_TRY(launch_permute_f64(ctx, n, 1, pii, g->int_of, pi));
+  std::vector<uint64_t> h((size_t)L + 2);
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(h.data(), cnt, 8 * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int32_t l = 0; l <= L; ++l) counts[l] = h[l];
+  if (h[L + 1] > (uint64_t)cap)
+    return fail(ctx, ES_EOVERFLOW, "%llu entries above the threshold, capacity %lld", (unsigned long long)h[L + 1],
+                (long long)cap);
+  return ES_OK;
 }
 
 es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, int32_t alloc,
@@ -162,6 +207,8 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   if (o->alloc == ES_ALLOC_LEARNED && !(o->v_floor_ratio >= 0.0 && o->v_floor_ratio <= 1.0))
     return fail(ctx, ES_EINVAL, "v_floor_ratio=%g outside [0, 1]", o->v_floor_ratio);
   if (o->lde < 0 || o->lde > 2) return fail(ctx, ES_EINVAL, "lde=%d outside 0..2", o->lde);
+  if (!(o->sparse_eps >= 0.0 && o->sparse_eps < 1.0))
+    return fail(ctx, ES_EINVAL, "sparse_eps=%g outside [0, 1)", o->sparse_eps);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   const int32_t n = g->n;
   const int32_t L = num_levels(o->c, o->eps);
@@ -169,7 +216,26 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   if (!o->d_override && R + (double)n >= 9.2e18)
     return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
   es_status st;
-  auto* levels = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)(L + 1) * n, &st);
+  // sparse linearization: Algorithm 3 reads levels 0..min(3, L) of the source
+  // densely, so those stay dense next to the working slot
+  const bool sparse = o->sparse_eps > 0.0;
+  SparseLevels sp{};
+  int32_t dense_slots = L + 1;
+  if (sparse) {
+    const double sc = std::sqrt(o->c);
+    sp.theta = (1.0 - sc) * (1.0 - sc) * o->sparse_eps;
+    sp.nkeep = (o->lde && !o->d_override) ? std::min(L, 3) + 1 : 0;
+    sp.cap = sparse_capacity(n, g->m, L, sp.theta);
+    dense_slots = std::min(L + 1, sp.nkeep + 1);
+    sp.idx = (int32_t*)workspace(ctx, kWsSpIdx, sizeof(int32_t) * (size_t)sp.cap, &st);
+    if (!sp.idx) return st;
+    sp.val = (double*)workspace(ctx, kWsSpVal, sizeof(double) * (size_t)sp.cap, &st);
+    if (!sp.val) return st;
+    sp.cnt = (unsigned long long*)workspace(ctx, kWsSpCnt, sizeof(uint64_t) * (size_t)(L + 2), &st);
+    if (!sp.cnt) return st;
+  }
+  const SparseLevels* spp = sparse ? &sp : nullptr;
+  auto* levels = (double*)workspace(ctx, kWsLevels, sizeof(double) * (size_t)dense_slots * n, &st);
   if (!levels) return st;
   auto* pi = (double*)workspace(ctx, kWsPi, sizeof(double) * (size_t)n, &st);
   if (!pi) return st;
@@ -185,7 +251,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   if (!Dh) return st;
   hipEvent_t* ev = ctx->ev;
   ES_CHECK_HIP(ctx, hipEventRecord(ev[0], ctx->stream));
-  ES_TRY(launch_forward(ctx, g, g->h_int_of[u], o->c, L, levels, pi, q0, q1));
+  ES_TRY(launch_forward(ctx, g, g->h_int_of[u], o->c, L, levels, pi, q0, q1, spp));
   ES_CHECK_HIP(ctx, hipEventRecord(ev[1], ctx->stream));
   WalkTotals* tot = nullptr;
   int32_t lde_level = 0;
@@ -229,7 +295,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     ES_TRY(launch_permute_f64(ctx, n, 1, o->d_override, g->ext_of, Dh));
     ES_CHECK_HIP(ctx, hipEventRecord(ev[4], ctx->stream));
   }
-  ES_TRY(launch_backward(ctx, g, levels, L, Dh, o->c, sint, stmp));
+  ES_TRY(launch_backward(ctx, g, levels, L, Dh, o->c, sint, stmp, spp));
   ES_TRY(launch_permute_f64(ctx, n, 1, sint, g->int_of, s_out));
   ES_CHECK_HIP(ctx, hipEventRecord(ev[5], ctx->stream));
   if (stats) {
@@ -254,6 +320,18 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&s.ms_backward, ev[4], ev[5]));
     s.lde_source_level = lde_level;
     s.lde_source_zsum = lde_zsum;
+    if (sparse) {
+      unsigned long long kept = 0;
+      ES_CHECK_HIP(ctx, hipMemcpy(&kept, sp.cnt + L + 1, sizeof(kept), hipMemcpyDeviceToHost));
+      if (kept > sp.cap)
+        return fail(ctx, ES_EOVERFLOW, "%llu entries above the threshold, capacity %llu", kept,
+                    (unsigned long long)sp.cap);
+      s.level_entries = kept;
+      s.level_bytes = 12ull * kept + 8ull * (uint64_t)dense_slots * (uint64_t)n;
+    } else {
+      s.level_entries = (uint64_t)(L + 1) * (uint64_t)n;
+      s.level_bytes = 8ull * s.level_entries;
+    }
     *stats = s;
   }
   return ES_OK;

@@ -11,6 +11,9 @@
 // One workgroup of 256 lanes per row block: the block's column ids are streamed
 // coalesced, the gathered operands staged in LDS, then each row is reduced by a
 // group of lanes sized to the block's average row length.
+#include <algorithm>
+#include <cmath>
+
 #include "es_internal.h"
 
 namespace es {
@@ -93,6 +96,21 @@ struct BackEpi {
   __device__ __forceinline__ Row load(int32_t r) const { return Row{inv_din[r], D[r], pil[r]}; }
   __device__ __forceinline__ void apply(int32_t r, double acc, const Row& d) const {
     s_next[r] = sc * (d.inv_din * acc) + a * (d.D * d.pil);
+  }
+};
+
+// back pass of sparse linearization: the level term is added afterwards by
+// level_scatter_kernel for the stored entries only
+struct BackEpiSparse {
+  struct Row {
+    double inv_din;
+  };
+  double sc;
+  const double* __restrict__ inv_din;
+  double* __restrict__ s_next;
+  __device__ __forceinline__ Row load(int32_t r) const { return Row{inv_din[r]}; }
+  __device__ __forceinline__ void apply(int32_t r, double acc, const Row& d) const {
+    s_next[r] = sc * (d.inv_din * acc);
   }
 };
 
@@ -219,33 +237,184 @@ __global__ void backward_init_kernel(int32_t n, double a, const double* __restri
   s0[i] = a * (D[i] * piL[i]);
 }
 
+// ---- sparse linearization (Section 3.2, Lemma 2) ---------------------------
+//
+// After level l is computed densely, level_keep_kernel adds it to pi and
+// appends its entries > theta to one list shared by all levels: a block takes
+// kKeepPer x kKeepThreads consecutive rows, counts its kept entries with wave
+// ballots and reserves their slots with one atomic on the running total, so
+// level l's entries follow those of levels < l (their order within a level is
+// unspecified; each node appears at most once per level).
+
+constexpr int kKeepThreads = 256;
+constexpr int kKeepPer = 16;
+constexpr int kKeepRows = kKeepThreads * kKeepPer;
+
+__global__ __launch_bounds__(kKeepThreads) void level_keep_kernel(int32_t n, const double* __restrict__ lvl,
+                                                                  double theta, int first, double* __restrict__ pi,
+                                                                  int32_t* __restrict__ sp_idx,
+                                                                  double* __restrict__ sp_val, uint64_t cap,
+                                                                  unsigned long long* __restrict__ cnt_level,
+                                                                  unsigned long long* __restrict__ cnt_total) {
+  __shared__ uint32_t wave_cnt[kKeepThreads / 64];
+  __shared__ unsigned long long block_base;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kKeepRows + threadIdx.x;
+  double v[kKeepPer];
+  unsigned long long bal[kKeepPer];
+  uint32_t kept = 0;
+#pragma unroll
+  for (int t = 0; t < kKeepPer; ++t) {
+    const int64_t i = r0 + (int64_t)t * kKeepThreads;
+    double x = 0.0;
+    if (i < n) {
+      x = lvl[i];
+      pi[i] = first ? x : pi[i] + x;
+    }
+    v[t] = x;
+    bal[t] = __ballot(x > theta);
+    kept += (uint32_t)__popcll(bal[t]);
+  }
+  if (lane == 0) wave_cnt[wave] = kept;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kKeepThreads / 64; ++w) tot += wave_cnt[w];
+    unsigned long long base = 0;
+    if (tot) {
+      base = atomicAdd(cnt_total, (unsigned long long)tot);
+      atomicAdd(cnt_level, (unsigned long long)tot);
+    }
+    block_base = base;
+  }
+  __syncthreads();
+  unsigned long long pos = block_base;
+  for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int t = 0; t < kKeepPer; ++t) {
+    if ((bal[t] >> lane) & 1ull) {
+      const unsigned long long p = pos + (unsigned long long)__popcll(bal[t] & below);
+      if (p < cap) {
+        sp_idx[p] = (int32_t)(r0 + (int64_t)t * kKeepThreads);
+        sp_val[p] = v[t];
+      }
+    }
+    pos += (unsigned long long)__popcll(bal[t]);
+  }
+}
+
+// [first, end) of level l in the list, clamped to the capacity
+__device__ __forceinline__ void level_range(int32_t l, const unsigned long long* cnt, uint64_t cap,
+                                            unsigned long long* first, unsigned long long* end) {
+  unsigned long long b = 0;
+  for (int32_t k = 0; k < l; ++k) b += cnt[k];
+  const unsigned long long e = b + cnt[l];
+  *first = b < cap ? b : cap;
+  *end = e < cap ? e : cap;
+}
+
+// s(j) += a D(j) pi^l(j) over the stored entries of level l
+__global__ void level_scatter_kernel(int32_t l, const unsigned long long* __restrict__ cnt, uint64_t cap,
+                                     const int32_t* __restrict__ sp_idx, const double* __restrict__ sp_val,
+                                     const double* __restrict__ D, double a, double* __restrict__ s) {
+  __shared__ unsigned long long range[2];
+  if (threadIdx.x == 0) level_range(l, cnt, cap, &range[0], &range[1]);
+  __syncthreads();
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long p = range[0] + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < range[1];
+       p += stride) {
+    const int32_t j = sp_idx[p];
+    s[j] = s[j] + a * (D[j] * sp_val[p]);
+  }
+}
+
+// ids of the whole list, internal -> external
+__global__ void sparse_ids_kernel(int32_t L, const unsigned long long* __restrict__ cnt, uint64_t cap,
+                                  const int32_t* __restrict__ ext_of, int32_t* __restrict__ sp_idx) {
+  __shared__ unsigned long long end;
+  if (threadIdx.x == 0) {
+    unsigned long long first;
+    level_range(L, cnt, cap, &first, &end);
+  }
+  __syncthreads();
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < end; p += stride)
+    sp_idx[p] = ext_of[sp_idx[p]];
+}
+
+__global__ void fill_u64_kernel(int64_t count, unsigned long long* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+__global__ void fill_f64_kernel(int64_t count, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+
+// blocks for a grid-stride pass over at most `count` list entries
+int scatter_blocks(uint64_t count) {
+  const uint64_t b = (count + 255) / 256;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, 1024));
+}
+
 }  // namespace
 
+uint64_t sparse_capacity(int32_t n, int64_t m, int32_t L, double theta) {
+  const double dense = (double)(L + 1) * (double)n;
+  // kept entries exceed theta and the levels' mass is at most 1 plus the
+  // fixed-point rounding of the forward pass (below 2^-62 per edge and level)
+  const double slack = (double)(L + 1) * ((double)m + (double)n) * 0x1p-62;
+  const double bound = std::floor((1.0 + slack) / theta) + 1.0;
+  return (uint64_t)(bound < dense ? bound : dense);
+}
+
+es_status launch_sparse_ids(es_ctx* ctx, const es_graph* g, int32_t L, const SparseLevels& sp) {
+  sparse_ids_kernel<<<scatter_blocks(sp.cap), 256, 0, ctx->stream>>>(L, sp.cnt, sp.cap, g->ext_of, sp.idx);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
 es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels, double* pi,
-                         int64_t* q0, int64_t* q1) {
+                         int64_t* q0, int64_t* q1, const SparseLevels* sp) {
   const int32_t n = g->n;
   const double sc = std::sqrt(c);
   const int tb = 256;
   const int nb = ceil_div(n, tb);
-  forward_init_kernel<<<nb, tb, 0, ctx->stream>>>(n, u, 1.0 - sc, g->inv_din, levels, q0);
+  // dense: level l in slot l; sparse: levels below nkeep in their slots, the rest share slot nkeep
+  auto slot = [&](int32_t l) -> double* {
+    const int32_t k = (sp && l >= sp->nkeep) ? sp->nkeep : l;
+    return levels + (int64_t)k * n;
+  };
+  const int kb = ceil_div(n, kKeepRows);
+  if (sp) fill_u64_kernel<<<ceil_div(L + 2, tb), tb, 0, ctx->stream>>>(L + 2, sp->cnt);
+  forward_init_kernel<<<nb, tb, 0, ctx->stream>>>(n, u, 1.0 - sc, g->inv_din, slot(0), q0);
+  if (sp)
+    level_keep_kernel<<<kb, kKeepThreads, 0, ctx->stream>>>(n, slot(0), sp->theta, 1, pi, sp->idx, sp->val,
+                                                            sp->cap, sp->cnt, sp->cnt + L + 1);
   int64_t* qp = q0;
   int64_t* qn = q1;
   for (int32_t l = 1; l <= L; ++l) {
     FwdGather ga{qp};
-    FwdEpi ep{sc, g->inv_din, levels + (int64_t)l * n, qn};
+    FwdEpi ep{sc, g->inv_din, slot(l), qn};
     if (g->fwd.nblocks > 0)
       spmv_pull_kernel<int64_t, FwdGather, FwdEpi><<<g->fwd.nblocks, kSpmvThreads, 0, ctx->stream>>>(
           g->fwd.blocks, g->out_off, g->out_idx, ga, ep, (int64_t*)g->fwd.partials, g->fwd.long_p0, g->fwd.long_nch,
           g->fwd.counters);
+    if (sp)
+      level_keep_kernel<<<kb, kKeepThreads, 0, ctx->stream>>>(n, slot(l), sp->theta, 0, pi, sp->idx, sp->val,
+                                                              sp->cap, sp->cnt + l, sp->cnt + L + 1);
     std::swap(qp, qn);
   }
-  sum_levels_kernel<<<nb, tb, 0, ctx->stream>>>(n, L, levels, pi);
+  if (!sp) sum_levels_kernel<<<nb, tb, 0, ctx->stream>>>(n, L, levels, pi);
   ES_CHECK_HIP(ctx, hipGetLastError());
   return ES_OK;
 }
 
 es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D, double c,
-                          double* s, double* s_tmp) {
+                          double* s, double* s_tmp, const SparseLevels* sp) {
   const int32_t n = g->n;
   const double sc = std::sqrt(c);
   const double a = 1.0 / (1.0 - sc);
@@ -254,6 +423,23 @@ es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, 
   // ping-pong so that level L lands in s
   double* cur = (L % 2 == 0) ? s : s_tmp;
   double* nxt = (L % 2 == 0) ? s_tmp : s;
+  if (sp) {
+    const int sb = scatter_blocks(std::min<uint64_t>(sp->cap, (uint64_t)n));
+    fill_f64_kernel<<<nb, tb, 0, ctx->stream>>>(n, cur);
+    level_scatter_kernel<<<sb, 256, 0, ctx->stream>>>(L, sp->cnt, sp->cap, sp->idx, sp->val, D, a, cur);
+    for (int32_t l = 1; l <= L; ++l) {
+      BackGather ga{cur};
+      BackEpiSparse ep{sc, g->inv_din, nxt};
+      if (g->back.nblocks > 0)
+        spmv_pull_kernel<double, BackGather, BackEpiSparse><<<g->back.nblocks, kSpmvThreads, 0, ctx->stream>>>(
+            g->back.blocks, g->in_off, g->in_idx, ga, ep, (double*)g->back.partials, g->back.long_p0,
+            g->back.long_nch, g->back.counters);
+      level_scatter_kernel<<<sb, 256, 0, ctx->stream>>>(L - l, sp->cnt, sp->cap, sp->idx, sp->val, D, a, nxt);
+      std::swap(cur, nxt);
+    }
+    ES_CHECK_HIP(ctx, hipGetLastError());
+    return ES_OK;
+  }
   backward_init_kernel<<<nb, tb, 0, ctx->stream>>>(n, a, D, levels + (int64_t)L * n, cur);
   for (int32_t l = 1; l <= L; ++l) {
     BackGather ga{cur};

@@ -276,3 +276,53 @@ def test_rmat1m_local_exploitation(es, ctx, rmat1m):
     _, ref_pi = ox.forward_levels(og, u, wl.c, L)
     assert np.array_equal(host(pi).view(np.uint64), ref_pi.view(np.uint64))
     _lde_full(es, ctx, g, og, u, wl.c, wl.eps, SINGLE_R_SCALE, wl.seed_walk, ref_pi, lv, L)
+
+
+def test_rmat1m_sparse_linearization(es, ctx, rmat1m):
+    """Sparse linearization (Section 3.2, Lemma 2) at eps_s = eps = 1e-6: the
+    kept entries of all levels bit for bit, the back-accumulation from them
+    with a seeded diagonal over all n within 1e-9, and the sampled query
+    within eps_s below the dense one with the same walks."""
+    wl, g, og, sources = rmat1m
+    u = int(sources[3])
+    c, eps = wl.c, wl.eps
+    L = ox.num_levels(c, eps)
+    cap = es.es_sparse_capacity(g.n, g.m, L, c, eps)
+    idx = torch.empty(cap, dtype=torch.int32, device="cuda")
+    val = torch.empty(cap, dtype=torch.float64, device="cuda")
+    counts = es.es_forward_sparse(ctx, g, u, c, L, eps, idx, val)
+    ref_lv, ref_pi = ox.forward_levels(og, u, c, L)
+    theta = ox.sparse_threshold(c, eps)
+    gi, gv = host(idx), host(val)
+    pos = 0
+    for l in range(L + 1):
+        want = np.flatnonzero(ref_lv[l] > theta)
+        assert counts[l] == len(want), l
+        order = np.argsort(gi[pos:pos + counts[l]])
+        assert np.array_equal(gi[pos:pos + counts[l]][order], want), l
+        assert np.array_equal(gv[pos:pos + counts[l]][order].view(np.uint64), ref_lv[l][want].view(np.uint64)), l
+        pos += counts[l]
+    say(f"  u={u}: {pos} entries kept of {(L + 1) * g.n} (capacity {cap})")
+
+    kept = ox.sparsify_levels(ref_lv, theta)
+    drng = np.random.default_rng(3000)
+    D_seed = drng.uniform(1.0 - c, 1.0, g.n)
+    D_seed[og.din == 0] = 1.0
+    D_seed[og.din == 1] = 1.0 - c
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, 1, 1.0, d_override=torch.as_tensor(D_seed).cuda(),
+                                                      sparse_eps=eps), s)
+    ref_s = ox.back_accumulate(og, kept, D_seed, c)
+    err = np.abs(host(s) - ref_s).max()
+    say(f"  seeded diagonal: max |s - s_ref| = {err:.2e}, {st.level_bytes / 1e6:.1f} MB of levels")
+    assert err <= S_TOL
+    assert st.level_entries == pos
+
+    s_d = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st_d = es.es_single_source(ctx, g, u, es.make_opts(c, eps, wl.seed_walk, SINGLE_R_SCALE), s_d)
+    st_s = es.es_single_source(ctx, g, u, es.make_opts(c, eps, wl.seed_walk, SINGLE_R_SCALE, sparse_eps=eps), s)
+    assert st_s.pairs == st_d.pairs and st_s.meets == st_d.meets
+    diff = host(s_d) - host(s)
+    say(f"  sampled: dense - sparse in [{diff.min():.2e}, {diff.max():.2e}]; "
+        f"levels {st_s.level_bytes / 1e6:.1f} MB vs {st_d.level_bytes / 1e6:.1f} MB dense")
+    assert diff.min() >= -1e-12 and diff.max() <= eps
