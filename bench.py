@@ -65,7 +65,7 @@ def parse():
                    help="rmat42m: budget multiple of the pi^2 reference run that errors are measured against")
     p.add_argument("--hip-graph", type=int, default=1)
     p.add_argument("--no-lde", action="store_true",
-                   help="skip the Algorithm 3 (local deterministic exploitation) lines")
+                   help="skip the Algorithm 3 (local deterministic exploitation) and sparse linearization lines")
     return p.parse_args()
 
 
@@ -220,7 +220,8 @@ def learned_main(args):
     training graphs (none of them the evaluation graph).  Both allocations
     are timed on the same sources at the same r_scale; their accuracy is
     the MaxError against a pi^2 run with --ref-factor times the budget and
-    another walk seed, at equal total pairs."""
+    another walk seed, at equal total pairs.  Algorithm 3 (reduced) and sparse
+    linearization (eps_s = eps) run on the same sources as further lines."""
     import numpy as np
     import torch
 
@@ -259,34 +260,37 @@ def learned_main(args):
     idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
     val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
 
-    def query(u, alloc, seed, r_scale, out, lde=0):
-        st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc, lde=lde), out)
+    def query(u, alloc, seed, r_scale, out, lde=0, sparse_eps=0.0):
+        st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc, lde=lde,
+                                                         sparse_eps=sparse_eps), out)
         es.es_topk(ctx, out, g.n, u, args.topk, idx, val)
         return st
 
     timed = {}
-    variants = (("pi2", es.ES_ALLOC_PI2, 0), ("learned", es.ES_ALLOC_LEARNED, 0),
-                ("pi2_lde_reduced", es.ES_ALLOC_PI2, es.ES_LDE_REDUCED))
-    for name, alloc, lde in variants:
+    variants = (("pi2", es.ES_ALLOC_PI2, 0, 0.0), ("learned", es.ES_ALLOC_LEARNED, 0, 0.0),
+                ("pi2_lde_reduced", es.ES_ALLOC_PI2, es.ES_LDE_REDUCED, 0.0),
+                ("pi2_sparse", es.ES_ALLOC_PI2, 0, eps),
+                ("pi2_lde_reduced_sparse", es.ES_ALLOC_PI2, es.ES_LDE_REDUCED, eps))
+    for name, alloc, lde, sp_eps in variants:
         for i in range(args.warmup):
-            query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde)
+            query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde, sp_eps)
         torch.cuda.synchronize()
         stats = []
         t = time.perf_counter()
         for i in range(args.steps):
-            stats.append(query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde))
+            stats.append(query(sources[i % len(sources)], alloc, wl.seed_walk, args.r_scale, s, lde, sp_eps))
             torch.cuda.synchronize()
             log(f"# {name} step {i}: pairs={stats[-1].pairs} walk {stats[-1].ms_walk:.1f} ms")
         timed[name] = (time.perf_counter() - t, stats)
     # accuracy at equal total pairs against a larger-budget pi^2 run
     ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
-    acc = {name: [] for name, _, _ in variants}
-    pairs = {name: 0 for name, _, _ in variants}
+    acc = {name: [] for name, *_ in variants}
+    pairs = {name: 0 for name, *_ in variants}
     for u in sources[:4]:
         query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
         for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
-            for name, alloc, lde in variants:
-                st = query(u, alloc, seed, args.r_scale, s, lde)
+            for name, alloc, lde, sp_eps in variants:
+                st = query(u, alloc, seed, args.r_scale, s, lde, sp_eps)
                 acc[name].append(float((s - ref).abs().max()))
                 pairs[name] += st.pairs
         log(f"# accuracy u={u}: " + " ".join(f"{k} {v[-2:]}" for k, v in acc.items()))
@@ -305,9 +309,11 @@ def learned_main(args):
             "ms_budget": float(np.mean([x.ms_budget for x in st])),
             "ms_walk": float(np.mean([x.ms_walk for x in st])),
             "ms_backward": float(np.mean([x.ms_backward for x in st])),
+            "level_bytes_mean": float(np.mean([x.level_bytes for x in st])),
         }
 
     pl, pp, pr = summary("learned"), summary("pi2"), summary("pi2_lde_reduced")
+    ps, prs = summary("pi2_sparse"), summary("pi2_lde_reduced_sparse")
     el = timed["learned"][0]
     out = {
         "metric": "exact single-source SimRank queries/s at eps=1e-6 (learned walk budget)",
@@ -321,6 +327,9 @@ def learned_main(args):
         "learned": pl,
         "pi2": pp,
         "pi2_lde_reduced": pr,
+        "pi2_sparse": ps,
+        "pi2_lde_reduced_sparse": prs,
+        "sparse_eps": eps,
         "roofline_spmv": {
             "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
             "achieved": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -337,10 +346,16 @@ def learned_main(args):
             "mean_ratio_pi2_over_lde_reduced": float(np.mean(acc["pi2"]) / np.mean(acc["pi2_lde_reduced"])),
             "pairs_pi2": int(pairs["pi2"]), "pairs_learned": int(pairs["learned"]),
             "pairs_lde_reduced": int(pairs["pi2_lde_reduced"]),
+            "max_error_pi2_sparse": acc["pi2_sparse"],
+            "max_error_pi2_lde_reduced_sparse": acc["pi2_lde_reduced_sparse"],
         },
         "projected_full_budget_s_per_query": float(pl["pairs_per_query_mean"] / args.r_scale / pl["walk_pairs_per_s"]),
     }
     print(json.dumps(out), flush=True)
+
+
+def L_of(stats):
+    return int(stats[0]["L"] if isinstance(stats[0], dict) else stats[0].L)
 
 
 def main():
@@ -371,9 +386,9 @@ def main():
     idx = torch.empty(args.topk, dtype=torch.int32, device="cuda")
     val = torch.empty(args.topk, dtype=torch.float64, device="cuda")
 
-    def step(i, lde=0):
+    def step(i, lde=0, sparse_eps=0.0):
         u = int(sources[i % len(sources)])
-        opts = es.make_opts(c, eps, wl.seed_walk, args.r_scale, lde=lde)
+        opts = es.make_opts(c, eps, wl.seed_walk, args.r_scale, lde=lde, sparse_eps=sparse_eps)
         st = es.es_single_source(ctx, g, u, opts, s)
         es.es_topk(ctx, s, g.n, u, args.topk, idx, val)
         return st
@@ -413,6 +428,39 @@ def main():
             }
             log(f"# lde {name}: {lde_out[name]['queries_per_s']:.3f} queries/s, "
                 f"{lde_out[name]['pairs_per_query_mean']:.3g} pairs/query")
+    # sparse linearization (Section 3.2, Lemma 2) with eps_s = eps, alone and
+    # with Algorithm 3 (reduced): the paper's optimized method
+    sparse_out = {}
+    if not args.no_lde:
+        ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        st_dense = step(0)
+        ref.copy_(s)
+        dense_bytes = int(st_dense.level_bytes)
+        sparse_out = {"sparse_eps": eps, "dense_level_bytes": dense_bytes,
+                      "capacity_entries": es.es_sparse_capacity(g.n, g.m, L_of(stats), c, eps)}
+        for name, mode in (("pi2", 0), ("pi2_lde_reduced", es.ES_LDE_REDUCED)):
+            step(0, mode, eps)
+            torch.cuda.synchronize()
+            diff = (ref - s) if mode == 0 else None
+            lst = []
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                lst.append(step(i, mode, eps))
+                torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            sparse_out[name] = {
+                "queries_per_s": args.steps / el,
+                "level_entries_mean": float(np.mean([x.level_entries for x in lst])),
+                "level_bytes_mean": float(np.mean([x.level_bytes for x in lst])),
+                "ms_forward": float(np.mean([x.ms_forward for x in lst])),
+                "ms_backward": float(np.mean([x.ms_backward for x in lst])),
+                "pairs_per_query_mean": float(np.mean([x.pairs for x in lst])),
+            }
+            if diff is not None:
+                sparse_out[name]["dense_minus_sparse_max_source0"] = float(diff.max())
+                sparse_out[name]["dense_minus_sparse_min_source0"] = float(diff.min())
+            log(f"# sparse {name}: {sparse_out[name]['queries_per_s']:.3f} queries/s, "
+                f"levels {sparse_out[name]['level_bytes_mean'] / 1e6:.1f} MB (dense {dense_bytes / 1e6:.1f} MB)")
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
@@ -473,6 +521,8 @@ def main():
     }
     if lde_out:
         out["lde"] = lde_out
+    if sparse_out:
+        out["sparse"] = sparse_out
     if not args.no_cpu_baseline:
         log("# cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, src, dst, int(sources[0]), args.r_scale, args.cpu_sample_pairs)
