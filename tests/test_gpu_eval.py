@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import workloads
+from oracle import exactsim as ox
 from oracle import simrank as sr
 from oracle.graph import OracleGraph
 
@@ -87,3 +88,31 @@ def test_evaluation_protocol(es, ctx, name):
     # the optimizations of Section 3: Algorithm 3 lowers the error at equal pairs
     assert rows["pi^2 + Alg. 3 as printed"][0] < rows["pi^2 allocation"][0]
     assert rows["pi^2 + Alg. 3 reduced"][3] < rows["pi^2 allocation"][3]
+
+
+def test_paper_budget_chung_lu(es, ctx):
+    """The paper's own sample budget (r_scale = 1, R = 6 ln n / ((1 - sqrt c)^4
+    eps^2)) on Chung-Lu 2,000 / 20,000 at eps = 1e-4, the workload's source
+    u = 0 and two more: Theorem 1's guarantee MaxError <= eps against the
+    Power Method, for Algorithm 1+2 and for Algorithm 3 (reduced) with sparse
+    linearization."""
+    wl = workloads.CHUNG_LU_2K
+    src, dst = wl.graph()
+    og = OracleGraph(wl.n, src, dst)
+    g = es.Graph(ctx, wl.n, src, dst)
+    S = sr.power_method(og, wl.c, 60)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    say(f"[{wl.name}] eps={wl.eps} r_scale=1 (the paper's R = {ox.total_samples(g.n, wl.c, wl.eps):.4g})")
+    for u in (0, 17, 1234):
+        for label, lde, sp in (("Alg. 1+2", es.ES_LDE_OFF, 0.0), ("Alg. 3 reduced + sparse", es.ES_LDE_REDUCED, wl.eps)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = es.es_single_source(ctx, g, u, es.make_opts(wl.c, wl.eps, wl.seed_walk, 1.0, lde=lde,
+                                                            sparse_eps=sp), s)
+            el = time.perf_counter() - t
+            v = s.cpu().numpy()
+            err = sr.max_error(v, S[:, u])
+            prec = sr.precision_at_k(v, S[:, u], u, K)
+            say(f"  u={u:5d} {label:24s} MaxError {err:.3e} Prec@500 {prec:.4f} pairs {st.pairs:.4g} {el:.2f} s")
+            assert err <= wl.eps
+            assert prec >= 0.99
