@@ -555,6 +555,9 @@ def main():
         "roofline": {
             "kernel": "walk_pairs_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
             "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS, "traffic": traffic,
+            # L2 fills from the memory fabric per second (Infinity-Cache hits included), against HBM peak
+            "traffic_gbs": None if traffic is None else traffic / float(walk_s.mean()) / 1e9,
+            "traffic_frac_of_hbm_peak": None if traffic is None else traffic / float(walk_s.mean()) / 1e9 / PEAK_HBM_GBS,
         },
         "roofline_spmv": {
             "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
