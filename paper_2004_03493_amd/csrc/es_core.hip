@@ -19,7 +19,8 @@ __global__ void walk_adj_kernel(int64_t m, const int32_t* __restrict__ in_off, c
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = in_idx[e];
     const int32_t o = in_off[v];
-    adj[e] = WalkEntry{v, o, in_off[v + 1] - o, 0};
+    const int32_t d = in_off[v + 1] - o;
+    adj[e] = WalkEntry{d > 0 ? o : -1 - v, d, 0, 0};
   }
 }
 

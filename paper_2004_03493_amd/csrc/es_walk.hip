@@ -295,22 +295,23 @@ struct WalkArgs {
   const WalkEntry* __restrict__ adj;    // in-CSR entries with their own rows
 };
 
-// A walk's position: node id and its in-CSR row (offset, in-degree).
+// A walk's position: its node's key (row offset, or -1 - id for a node
+// without in-neighbours; unique per node) and in-degree.
 struct Pos {
-  int32_t id, off, deg;
+  int32_t key, deg;
 };
 
 // One step of both walks; returns 1 = met, 0 = moved without meeting, -1 = a
-// walk is stuck.  Each walk reads one 16-byte entry of its current row, which
-// already holds the next node's row.
+// walk is stuck.  Each walk reads one entry of its current row, which is the
+// next node's row.
 __device__ __forceinline__ int walk_step(const WalkEntry* __restrict__ adj, Pos& x, Pos& y, uint64_t wx,
                                          uint64_t wy) {
   if (x.deg == 0 || y.deg == 0) return -1;
-  const WalkEntry ex = adj[x.off + mulhi_index(wx, (uint32_t)x.deg)];
-  const WalkEntry ey = adj[y.off + mulhi_index(wy, (uint32_t)y.deg)];
-  x = Pos{ex.id, ex.off, ex.deg};
-  y = Pos{ey.id, ey.off, ey.deg};
-  return x.id == y.id ? 1 : 0;
+  const WalkEntry ex = adj[x.key + mulhi_index(wx, (uint32_t)x.deg)];
+  const WalkEntry ey = adj[y.key + mulhi_index(wy, (uint32_t)y.deg)];
+  x = Pos{ex.key, ex.deg};
+  y = Pos{ey.key, ey.deg};
+  return x.key == y.key ? 1 : 0;
 }
 
 // Sum the per-lane work counters over the wave, one atomic each (wave-uniform call).
@@ -336,7 +337,8 @@ __device__ __forceinline__ void flush_work(WalkTotals* tot, uint32_t nblocks, ui
 // l = nonstop[k] steps without stopping (lifetime l + T), and a meeting at a
 // step t <= l ends the pair without counting.
 // Eight waves per SIMD (at most 64 VGPRs) measured faster than the looser
-// register budget the compiler picks by itself, despite a few spills.
+// register budget the compiler picks by itself, so the state a lane carries
+// from one iteration to the next is kept small: 32-bit where the range allows.
 template <bool kBuckets, bool kNonstop>
 __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void walk_pairs_kernel(
     WalkArgs a) {
@@ -349,15 +351,20 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
   uint64_t run = total / (waves * 64ull * 4ull);
   run = run < kWalkMinRun ? kWalkMinRun : (run > kWalkMaxRun ? kWalkMaxRun : run);
   const unsigned long long chunk = 64ull * run;
-  // meeting count held for node cnt_node, flushed when the lane moves on
+  // meeting count held for node cnt_node, flushed when the lane moves on (or
+  // before the 32-bit count could wrap)
   int32_t cnt_node = -1;
-  unsigned long long cnt = 0;
+  uint32_t cnt = 0;
   int32_t cnt_bucket = 0;      // buckets only
   uint64_t next_thr = 0;       // buckets only: first threshold above the cached bucket
   uint32_t nblocks = 0, nsteps = 0;  // work counters for the roofline, flushed per chunk
-  // lifetimes of the four pairs 4q..4q+3 of count index lk, 16 bits each (T <= 4096)
-  int32_t lk = -1;
-  uint64_t lq = 0, lt = 0;
+  auto flush_meets = [&]() {
+    if (cnt) {
+      if constexpr (kBuckets) atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], (unsigned long long)cnt);
+      else atomicAdd(&a.M[cnt_node], (unsigned long long)cnt);
+      atomicAdd(&a.tot->meets, (unsigned long long)cnt);
+    }
+  };
   auto lifetime = [&](uint64_t u) -> uint64_t {
     uint64_t T = 0;
 #pragma unroll
@@ -371,23 +378,31 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     if (lane == 0) c0 = atomicAdd(&a.tot->cursor, chunk);
     c0 = __shfl(c0, 0, 64);
     if (c0 >= total) break;
-    // this lane's run of samples [i, iend)
+    // this lane's run of samples: nleft of them from i
     uint64_t i = c0 + (uint64_t)lane * run;
-    const uint64_t iend = (i + run < total) ? i + run : total;
-    int32_t p = 0;
-    uint64_t pbeg = 0, pend = 0;
-    // the node of slot p: count index, first sample, and its position in the graph
-    int32_t pk = 0;
-    uint64_t prb = 0;
-    Pos pstart{0, 0, 0};
-    auto load_node = [&]() {
+    uint32_t nleft = i < total ? (uint32_t)(total - i < run ? total - i : run) : 0u;
+    // lifetimes of the four pairs of one quad of count index lk, 16 bits each
+    // (T <= 4096); cached within the chunk only, so the low 32 bits of the
+    // quad index name it
+    int32_t lk = -1;
+    uint32_t lq = 0;
+    uint64_t lt = 0;
+    // slot p of the active list: count index pk, its stream id, the pair index
+    // of sample s (s + pdelta), its last sample + 1, and its start position
+    int32_t p = 0, pk = 0;
+    uint32_t pkc = 0;
+    uint64_t pend = 0, pdelta = 0;
+    Pos pstart{0, 0};
+    auto load_node = [&](uint64_t pbeg) {
       pk = a.active[p];
-      prb = a.r_begin ? a.r_begin[pk] : 0ull;
+      pdelta = (a.r_begin ? a.r_begin[pk] : 0ull) - pbeg;
       const int32_t kg = a.to_graph ? a.to_graph[pk] : pk;
       const int32_t o = a.in_off[kg];
-      pstart = Pos{kg, o, a.in_off[kg + 1] - o};
+      const int32_t d = a.in_off[kg + 1] - o;
+      pstart = Pos{d > 0 ? o : -1 - kg, d};
+      pkc = (uint32_t)(a.to_stream ? a.to_stream[pk] : pk);
     };
-    if (i < iend) {
+    if (nleft) {
       // last active slot whose prefix is <= i
       int32_t lo = 0, hi = nact;  // prefix[lo] <= i < prefix[hi]
       while (hi - lo > 1) {
@@ -396,51 +411,45 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
         else hi = mid;
       }
       p = lo;
-      pbeg = a.prefix[p];
       pend = a.prefix[p + 1];
-      load_node();
+      load_node(a.prefix[p]);
     }
     bool in_pair = false;
-    int32_t k = 0, t = 0, T = 0;
-    Pos x{0, 0, 0}, y{0, 0, 0};
+    int32_t t = 0, T = 0;
+    Pos x{0, 0}, y{0, 0};
     int32_t nsl = 0;  // non-stop steps of the current pair
-    uint64_t r = 0, kc = 0;
     for (;;) {
       // out of a pair: start the next one; pairs whose cached lifetime is 0
       // end at once, a pair without a cached lifetime needs its lifetime block
       bool need_life = false;
       if (!in_pair) {
-        while (i < iend) {
+        while (nleft) {
           if (i >= pend) {
+            uint64_t pbeg;
             do {
               ++p;
               pbeg = pend;
               pend = a.prefix[p + 1];
             } while (i >= pend);
-            load_node();
+            load_node(pbeg);
           }
-          const uint64_t rr = prb + (i - pbeg);
-          if (pk == lk && (rr >> 2) == lq) {
+          const uint64_t rr = i + pdelta;
+          if (pk == lk && (uint32_t)(rr >> 2) == lq) {
             int32_t TT = (int32_t)((lt >> (16 * (rr & 3))) & 0xffffu);
             ++i;
+            --nleft;
             if constexpr (kNonstop) {
               nsl = a.nonstop[pk];
               TT += nsl;
             }
             if (TT == 0) continue;  // both walks stop at once: no meeting
-            k = pk;
-            r = rr;
             T = TT;
-            kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
             x = pstart;
             y = pstart;
             t = 0;
             in_pair = true;
             break;
           }
-          k = pk;
-          r = rr;
-          kc = (uint64_t)(a.to_stream ? a.to_stream[k] : k);
           need_life = true;
           break;
         }
@@ -448,16 +457,19 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       const bool busy = in_pair || need_life;
       if (!__any(busy)) break;
       if (!busy) continue;
+      // the pair's index: its sample is i - 1 while it walks (i moved on when
+      // it started) and i while its lifetime block is due
+      const uint64_t r = i + pdelta - (in_pair ? 1ull : 0ull);
       // one Philox block per lane and iteration: a lifetime block (k, q, 0, 1)
       // or the movement block (k, r, j, 0) of steps 2j+1 and 2j+2
       const uint64_t c1 = need_life ? (r >> 2) : r;
       const uint64_t c2 = need_life ? 0ull : (uint64_t)(t >> 1);
       const uint64_t c3 = need_life ? 1ull : 0ull;
-      const Words w = philox4x64_10(kc, c1, c2, c3, a.seed, 0ull);
+      const Words w = philox4x64_10((uint64_t)pkc, c1, c2, c3, a.seed, 0ull);
       ++nblocks;
       if (need_life) {
-        lk = k;
-        lq = r >> 2;
+        lk = pk;
+        lq = (uint32_t)(r >> 2);
         lt = lifetime(w.w0) | (lifetime(w.w1) << 16) | (lifetime(w.w2) << 32) | (lifetime(w.w3) << 48);
         continue;  // the pair starts from the cache on the next iteration
       }
@@ -480,25 +492,19 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
         in_pair = false;
         if (res > 0) {
           if constexpr (!kBuckets) {
-            if (k == cnt_node) {
+            if (pk == cnt_node && cnt < 0x7fffffffu) {
               ++cnt;
             } else {
-              if (cnt) {
-                atomicAdd(&a.M[cnt_node], cnt);
-                atomicAdd(&a.tot->meets, cnt);
-              }
-              cnt_node = k;
+              flush_meets();
+              cnt_node = pk;
               cnt = 1;
             }
           } else {
-            if (k == cnt_node && r < next_thr) {
+            if (pk == cnt_node && r < next_thr && cnt < 0x7fffffffu) {
               ++cnt;
             } else {
-              if (cnt) {
-                atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], cnt);
-                atomicAdd(&a.tot->meets, cnt);
-              }
-              const uint64_t* Tk = a.T + (int64_t)k * a.B;
+              flush_meets();
+              const uint64_t* Tk = a.T + (int64_t)pk * a.B;
               int32_t lo = 0, hi = a.B;  // first threshold above r
               while (lo < hi) {
                 const int32_t mid = (lo + hi) >> 1;
@@ -507,7 +513,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
               }
               cnt_bucket = lo;
               next_thr = lo < a.B ? Tk[lo] : ~0ull;
-              cnt_node = k;
+              cnt_node = pk;
               cnt = 1;
             }
           }
@@ -518,11 +524,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     flush_work(a.tot, nblocks, nsteps);
     nblocks = nsteps = 0;
   }
-  if (cnt) {
-    if constexpr (kBuckets) atomicAdd(&a.M[(int64_t)cnt_node * a.B + cnt_bucket], cnt);
-    else atomicAdd(&a.M[cnt_node], cnt);
-    atomicAdd(&a.tot->meets, cnt);
-  }
+  flush_meets();
 }
 
 __global__ void diag_kernel(int32_t n, const uint64_t* __restrict__ Rk, const uint64_t* __restrict__ M,
