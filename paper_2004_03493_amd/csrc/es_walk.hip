@@ -365,10 +365,10 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       atomicAdd(&a.tot->meets, (unsigned long long)cnt);
     }
   };
-  auto lifetime = [&](uint64_t u) -> uint64_t {
-    uint64_t T = 0;
+  auto lifetime = [&](uint64_t u) -> uint32_t {
+    uint32_t T = 0;
 #pragma unroll
-    for (int q = 1; q <= kLifeRegs; ++q) T += u < a.thr[q] ? 1 : 0;  // thresholds decrease
+    for (int q = 1; q <= kLifeRegs; ++q) T += u < a.thr[q] ? 1u : 0u;  // thresholds decrease
     if (T == kLifeRegs)
       while ((int32_t)T < a.tmax && u < a.thr[T + 1]) ++T;
     return T;
@@ -470,7 +470,8 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       if (need_life) {
         lk = pk;
         lq = (uint32_t)(r >> 2);
-        lt = lifetime(w.w0) | (lifetime(w.w1) << 16) | (lifetime(w.w2) << 32) | (lifetime(w.w3) << 48);
+        lt = (uint64_t)(lifetime(w.w0) | (lifetime(w.w1) << 16)) |
+             ((uint64_t)(lifetime(w.w2) | (lifetime(w.w3) << 16)) << 32);
         continue;  // the pair starts from the cache on the next iteration
       }
       int st = walk_step(a.adj, x, y, w.w0, w.w1);
