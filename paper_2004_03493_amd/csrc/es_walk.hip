@@ -391,6 +391,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     // of sample s (s + pdelta), its last sample + 1, and its start position
     int32_t p = 0, pk = 0;
     uint32_t pkc = 0;
+    int32_t nsl = 0;  // non-stop variant: l(pk), the non-stop steps of pk's pairs
     uint64_t pend = 0, pdelta = 0;
     Pos pstart{0, 0};
     auto load_node = [&](uint64_t pbeg) {
@@ -401,6 +402,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       const int32_t d = a.in_off[kg + 1] - o;
       pstart = Pos{d > 0 ? o : -1 - kg, d};
       pkc = (uint32_t)(a.to_stream ? a.to_stream[pk] : pk);
+      if constexpr (kNonstop) nsl = a.nonstop[pk];
     };
     if (nleft) {
       // last active slot whose prefix is <= i
@@ -417,7 +419,6 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     bool in_pair = false;
     int32_t t = 0, T = 0;
     Pos x{0, 0}, y{0, 0};
-    int32_t nsl = 0;  // non-stop steps of the current pair
     for (;;) {
       // out of a pair: start the next one; pairs whose cached lifetime is 0
       // end at once, a pair without a cached lifetime needs its lifetime block
@@ -438,10 +439,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
             int32_t TT = (int32_t)((lt >> (16 * (rr & 3))) & 0xffffu);
             ++i;
             --nleft;
-            if constexpr (kNonstop) {
-              nsl = a.nonstop[pk];
-              TT += nsl;
-            }
+            if constexpr (kNonstop) TT += nsl;
             if (TT == 0) continue;  // both walks stop at once: no meeting
             T = TT;
             x = pstart;
