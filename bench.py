@@ -61,6 +61,8 @@ def parse():
                    help="single: the R-MAT 2^20 single-source line; batch64 / uneven: batched queries "
                         "against single-source queries on the same GPU; rmat42m: R-MAT n=4.2e7, m=1.4e9 "
                         "with the learned walk budget against the pi^2 rule")
+    p.add_argument("--no-accuracy", action="store_true",
+                   help="rmat42m: skip the accuracy comparison (timing lines only)")
     p.add_argument("--ref-factor", type=float, default=16.0,
                    help="rmat42m: budget multiple of the pi^2 reference run that errors are measured against")
     p.add_argument("--hip-graph", type=int, default=1)
@@ -286,7 +288,7 @@ def learned_main(args):
     ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
     acc = {name: [] for name, *_ in variants}
     pairs = {name: 0 for name, *_ in variants}
-    for u in sources[:4]:
+    for u in ([] if args.no_accuracy else sources[:4]):
         query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
         for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
             for name, alloc, lde, sp_eps in variants:
@@ -342,8 +344,9 @@ def learned_main(args):
             "v_floor_ratio": es.ES_LEARNED_FLOOR,
             "max_error_pi2": acc["pi2"], "max_error_learned": acc["learned"],
             "max_error_pi2_lde_reduced": acc["pi2_lde_reduced"],
-            "mean_ratio_pi2_over_learned": float(np.mean(acc["pi2"]) / np.mean(acc["learned"])),
-            "mean_ratio_pi2_over_lde_reduced": float(np.mean(acc["pi2"]) / np.mean(acc["pi2_lde_reduced"])),
+            "mean_ratio_pi2_over_learned": float(np.mean(acc["pi2"]) / np.mean(acc["learned"])) if acc["pi2"] else None,
+            "mean_ratio_pi2_over_lde_reduced":
+                float(np.mean(acc["pi2"]) / np.mean(acc["pi2_lde_reduced"])) if acc["pi2"] else None,
             "pairs_pi2": int(pairs["pi2"]), "pairs_learned": int(pairs["learned"]),
             "pairs_lde_reduced": int(pairs["pi2_lde_reduced"]),
             "max_error_pi2_sparse": acc["pi2_sparse"],
