@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=8)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--r-scale", type=float, default=1e-5)
+    p.add_argument("--r-scale", type=float, default=None,
+                   help="walk budget scale (default 1e-5 for single-source lines, 1e-7 for the batched ones)")
     p.add_argument("--topk", type=int, default=500)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-pairs", type=float, default=2e8)
@@ -412,6 +413,8 @@ def L_of(stats):
 
 def main():
     args = parse()
+    if args.r_scale is None:
+        args.r_scale = 1e-7 if args.workload in ("batch64", "uneven") else 1e-5
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
