@@ -197,6 +197,44 @@ def test_learned_allocation_gains_over_pi2(es, ctx, trained, cl2k):
     assert ratio > 1.15
 
 
+def test_learned_pairs_at_equal_error(es, ctx, trained, cl2k):
+    """The other side of the comparison: the total pairs the pi^2 allocation
+    needs to reach the learned allocation's MaxError, found by running pi^2 at
+    1x, 2x, 4x and 8x the budget and interpolating log MaxError against log
+    pairs (mean over sources and seeds, Power Method ground truth)."""
+    w, _, _ = trained
+    g, og = cl2k
+    S = sr.power_method(og, C, 60)
+    es.es_mlp_load(ctx, w)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eps, base = 1e-4, 1e-3
+    sources, seeds = (0, 5, 50, 300), range(6)
+
+    def run(alloc, r_scale):
+        errs, pairs = [], 0
+        for u in sources:
+            for seed in seeds:
+                st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, 700 + seed, r_scale, alloc=alloc), s)
+                errs.append(sr.max_error(s.cpu().numpy(), S[:, u]))
+                pairs += st.pairs
+        return float(np.mean(errs)), pairs
+
+    e_l, p_l = run(es.ES_ALLOC_LEARNED, base)
+    curve = [run(es.ES_ALLOC_PI2, base * f) for f in (1, 2, 4, 8)]
+    errs = np.array([e for e, _ in curve])
+    pairs = np.array([p for _, p in curve], dtype=np.float64)
+    say("  pi2: " + ", ".join(f"{p:.3g} pairs -> {e:.3e}" for e, p in curve) + f"; learned: {p_l:.3g} pairs -> {e_l:.3e}")
+    assert np.all(np.diff(errs) < 0)  # more pairs, smaller error
+    assert errs[-1] < e_l < errs[0]
+    # log-log interpolation between the two budgets that bracket e_l
+    k = int(np.searchsorted(-errs, -e_l))
+    x0, x1 = np.log(pairs[k - 1]), np.log(pairs[k])
+    y0, y1 = np.log(errs[k - 1]), np.log(errs[k])
+    p_eq = float(np.exp(x0 + (np.log(e_l) - y0) * (x1 - x0) / (y1 - y0)))
+    say(f"  pi2 reaches the learned MaxError with {p_eq:.3g} pairs: {p_eq / p_l:.2f}x the learned budget")
+    assert p_eq > 1.5 * p_l
+
+
 def test_learned_predictions_cached_per_network(es, ctx, trained, cl2k):
     """The predicted variances are cached in the graph per loaded network and
     decay: repeated queries agree bit for bit, other weights change the
