@@ -195,6 +195,18 @@ def batch_main(args):
         walk_ms += st.ms_walk
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t
+    # the same batch with sparse linearization (eps_s = eps): level storage of the whole batch
+    sp_opts = es.make_opts(c, eps, wl.seed_walk, args.r_scale, sparse_eps=eps)
+    es.es_batch(ctx, graphs, goq, sources, sp_opts, outs, use_hip_graph=bool(args.hip_graph))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sp_stats = []
+    for i in range(args.steps):
+        sp_stats.append(es.es_batch(ctx, graphs, goq, sources, sp_opts, outs, use_hip_graph=bool(args.hip_graph)))
+        torch.cuda.synchronize()
+    t_sparse = (time.perf_counter() - t) / args.steps
+    log(f"# sparse batch: {len(sources) / t_sparse:.2f} queries/s, levels {sp_stats[-1].level_bytes / 1e9:.3f} GB "
+        f"(dense {bstats[-1].level_bytes / 1e9:.3f} GB)")
     tuned = sorted({(g.n, es.es_batch_tuning(g, min(64, goq.count(gi)))) for gi, g in enumerate(graphs)})
     nq = len(sources)
     out = {
@@ -212,6 +224,9 @@ def batch_main(args):
         "single_source_pairs": int(pairs_single),
         "single_source_ms": {"forward": fwd_ms, "walk": walk_ms, "backward": back_ms, "total": t_single * 1e3},
         "tuned_width_rows": tuned,
+        "dense_level_bytes": int(bstats[-1].level_bytes),
+        "sparse": {"sparse_eps": eps, "queries_per_s": nq / t_sparse,
+                   "level_entries": int(sp_stats[-1].level_entries), "level_bytes": int(sp_stats[-1].level_bytes)},
     }
     print(json.dumps(out), flush=True)
 

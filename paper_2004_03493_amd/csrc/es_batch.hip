@@ -103,7 +103,7 @@ struct BackOp {
   const double* __restrict__ sprev;
   double* __restrict__ snext;
   const double* __restrict__ D;
-  const double* __restrict__ lvl;  // level L - l
+  const double* __restrict__ lvl;  // level L - l; NULL: sparse levels, added afterwards by a scatter
   double* __restrict__ acc;
   double sc, a;
   __device__ __forceinline__ V gather(const BEntry& E, int32_t col, int sub) const {
@@ -111,7 +111,8 @@ struct BackOp {
   }
   __device__ __forceinline__ void epi(const BEntry& E, int32_t r, int sub, V v) const {
     const int64_t i = E.base + (int64_t)r * E.B + sub;
-    snext[i] = sc * (E.inv_din[r] * v) + a * (D[i] * lvl[i]);
+    if (lvl) snext[i] = sc * (E.inv_din[r] * v) + a * (D[i] * lvl[i]);
+    else snext[i] = sc * (E.inv_din[r] * v);
   }
   __device__ __forceinline__ void long_add(const BEntry& E, int32_t slot, int sub, V v) const {
     atomicAdd(&acc[(E.long_base + slot) * kBatchMaxB + sub], v);
@@ -341,6 +342,7 @@ struct BatchPlan {
   uint64_t seed = 0;
   int32_t alloc = 0, small = 0;
   int32_t nq = 0;
+  double sparse_eps = 0;
   // device data
   BEntry* ents = nullptr;
   int32_t nent = 0;
@@ -447,13 +449,36 @@ struct BatchBuffers {
   uint64_t* Rmax;
   long long* acc;
   unsigned long long* sums;  // [0] pairs requested, [1] meets, [2] pairs simulated, [3] raw meets
+  SparseLevels sp;           // sparse linearization: the kept level entries (sp.idx NULL when dense)
 };
 
-es_status batch_buffers(es_ctx* ctx, const BatchPlan& p, BatchBuffers* b) {
+// Capacity of the kept entries of a batch: each source keeps at most its own bound.
+uint64_t batch_sparse_capacity(const BatchPlan& p, const std::vector<const es_graph*>& block_graphs, double theta) {
+  uint64_t cap = 0;
+  for (int32_t e = 0; e < p.nent; ++e)
+    cap += (uint64_t)p.kB[e] * sparse_capacity(block_graphs[e]->n, block_graphs[e]->m, p.L, theta);
+  return std::min<uint64_t>(cap, (uint64_t)(p.L + 1) * (uint64_t)p.NB);
+}
+
+es_status batch_buffers(es_ctx* ctx, const BatchPlan& p, BatchBuffers* b, double sparse_eps = 0.0,
+                        const std::vector<const es_graph*>* block_graphs = nullptr) {
   es_status st;
   const size_t NB = (size_t)p.NB;
   const size_t L1 = (size_t)p.L + 1;
-  b->levels = (double*)workspace(ctx, kWsLevels, 8 * NB * L1, &st);
+  b->sp = SparseLevels{};
+  if (sparse_eps > 0.0) {
+    // the level of the moment stays dense; the kept entries of all levels go to one list
+    const double sc = std::sqrt(p.c);
+    b->sp.theta = (1.0 - sc) * (1.0 - sc) * sparse_eps;
+    b->sp.cap = batch_sparse_capacity(p, *block_graphs, b->sp.theta);
+    b->sp.idx = (int32_t*)workspace(ctx, kWsSpIdx, sizeof(int32_t) * (size_t)b->sp.cap, &st);
+    if (!b->sp.idx) return st;
+    b->sp.val = (double*)workspace(ctx, kWsSpVal, sizeof(double) * (size_t)b->sp.cap, &st);
+    if (!b->sp.val) return st;
+    b->sp.cnt = (unsigned long long*)workspace(ctx, kWsSpCnt, sizeof(uint64_t) * (L1 + 1), &st);
+    if (!b->sp.cnt) return st;
+  }
+  b->levels = (double*)workspace(ctx, kWsLevels, 8 * NB * (sparse_eps > 0.0 ? 1 : L1), &st);
   if (!b->levels) return st;
   b->q[0] = (int64_t*)workspace(ctx, kWsQ0, 8 * NB, &st);
   if (!b->q[0]) return st;
@@ -494,17 +519,23 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
   dim3 egrid(p.max_nb_blocks, p.nent);
   zero_u64<<<1, 64, 0, stream>>>(4, b.sums);
   zero_u64<<<ceil_div(nacc, tb), tb, 0, stream>>>(nacc, (unsigned long long*)b.acc);
-  bat_forward_init<<<egrid, tb, 0, stream>>>(p.ents, p.src_int, 1.0 - sc, b.levels, b.q[0]);
+  const bool sparse = b.sp.idx != nullptr;
+  // dense: level l in slot l; sparse: every level in slot 0, its kept entries appended to b.sp
+  auto slot = [&](int32_t l) { return b.levels + (sparse ? 0 : (int64_t)l * NB); };
+  if (sparse) ES_TRY(launch_fill(ctx, p.L + 2, b.sp.cnt));
+  bat_forward_init<<<egrid, tb, 0, stream>>>(p.ents, p.src_int, 1.0 - sc, slot(0), b.q[0]);
+  if (sparse) ES_TRY(launch_level_keep(ctx, NB, slot(0), true, b.pi, b.sp, 0, p.L));
   const int spmm_f = ceil_div(p.ntf, kSpmmThreads / 64);
   const int spmm_b = ceil_div(p.ntb, kSpmmThreads / 64);
   for (int32_t l = 1; l <= p.L; ++l) {
-    FwdOp op{b.q[(l - 1) & 1], b.q[l & 1], b.levels + (int64_t)l * NB, b.acc, sc};
+    FwdOp op{b.q[(l - 1) & 1], b.q[l & 1], slot(l), b.acc, sc};
     if (p.ntf) spmm_kernel<FwdOp><<<spmm_f, kSpmmThreads, 0, stream>>>(p.tiles_fwd, p.ntf, p.ents, op);
     if (p.nlf)
       long_finish_kernel<FwdOp><<<ceil_div((int64_t)p.nlf * kBatchMaxB, tb), tb, 0, stream>>>(p.long_fwd, p.nlf,
                                                                                                p.ents, op);
+    if (sparse) ES_TRY(launch_level_keep(ctx, NB, slot(l), false, b.pi, b.sp, l, p.L));
   }
-  bat_sum_levels<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, p.L, b.levels, b.pi);
+  if (!sparse) bat_sum_levels<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, p.L, b.levels, b.pi);
   bat_budget<<<egrid, tb, 0, stream>>>(p.ents, b.pi, p.alloc, p.small, b.Rk);
   dim3 sgrid(ceil_div(p.max_n, tb / 64), p.nent);
   bat_sort_counts<<<sgrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.Rmax);
@@ -518,13 +549,20 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
   }
   bat_finish_diag<<<egrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.H, p.c, p.small, b.D, b.sums);
   // back-accumulation; level L lands in s[L & 1]
-  bat_back_init<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, a, b.D, b.levels + (int64_t)p.L * NB, b.s[0]);
+  if (sparse) {
+    ES_TRY(launch_fill(ctx, NB, b.s[0]));
+    ES_TRY(launch_level_scatter(ctx, NB, b.sp, p.L, b.D, a, b.s[0]));
+  } else {
+    bat_back_init<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, a, b.D, b.levels + (int64_t)p.L * NB, b.s[0]);
+  }
   for (int32_t l = 1; l <= p.L; ++l) {
-    BackOp op{b.s[(l - 1) & 1], b.s[l & 1], b.D, b.levels + (int64_t)(p.L - l) * NB, (double*)b.acc, sc, a};
+    BackOp op{b.s[(l - 1) & 1], b.s[l & 1], b.D, sparse ? nullptr : b.levels + (int64_t)(p.L - l) * NB,
+              (double*)b.acc, sc, a};
     if (p.ntb) spmm_kernel<BackOp><<<spmm_b, kSpmmThreads, 0, stream>>>(p.tiles_back, p.ntb, p.ents, op);
     if (p.nlb)
       long_finish_kernel<BackOp><<<ceil_div((int64_t)p.nlb * kBatchMaxB, tb), tb, 0, stream>>>(p.long_back, p.nlb,
                                                                                                 p.ents, op);
+    if (sparse) ES_TRY(launch_level_scatter(ctx, NB, b.sp, p.L - l, b.D, a, b.s[l & 1]));
   }
   bat_output<<<egrid, tb, 0, stream>>>(p.ents, b.s[p.L & 1], p.outs);
   ES_CHECK_HIP(ctx, hipGetLastError());
@@ -534,7 +572,7 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
 bool same_key(const BatchPlan& p, const BatchPlan& q) {
   return p.kg == q.kg && p.kB == q.kB && p.kW == q.kW && p.kG == q.kG && p.L == q.L && p.c == q.c &&
          p.eps == q.eps && p.r_scale == q.r_scale && p.seed == q.seed && p.alloc == q.alloc && p.small == q.small &&
-         p.nq == q.nq;
+         p.nq == q.nq && p.sparse_eps == q.sparse_eps;
 }
 
 // Build tiles and descriptors of a plan whose key fields are set.
@@ -714,7 +752,8 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI)
     return fail(ctx, o->alloc == ES_ALLOC_LEARNED ? ES_EUNSUPPORTED : ES_EINVAL, "allocation %d", o->alloc);
   if (o->lde != 0) return fail(ctx, ES_EUNSUPPORTED, "batches run Algorithm 2 only (lde = 0)");
-  if (o->sparse_eps != 0.0) return fail(ctx, ES_EUNSUPPORTED, "batches keep dense levels (sparse_eps = 0)");
+  if (!(o->sparse_eps >= 0.0 && o->sparse_eps < 1.0))
+    return fail(ctx, ES_EINVAL, "sparse_eps=%g outside [0, 1)", o->sparse_eps);
   es_batch_opts defaults{0, 1, 0, 0};
   const es_batch_opts& b = bo ? *bo : defaults;
   if (b.force_width && (b.force_width < 8 || b.force_width > 64 || (b.force_width & (b.force_width - 1))))
@@ -782,6 +821,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   key.alloc = o->alloc;
   key.small = o->exact_small_din;
   key.nq = nq;
+  key.sparse_eps = o->sparse_eps;
   BatchPlan* plan = nullptr;
   for (BatchPlan* p = ctx->plans; p; p = p->next)
     if (same_key(*p, key)) plan = p;
@@ -812,9 +852,14 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
     plan->next = ctx->plans;
     ctx->plans = plan;
   }
+  std::vector<const es_graph*> block_graphs;
+  for (auto& bl : blocks) block_graphs.push_back(bl.g);
+  // the kept entries are indexed by int32 flat positions
+  if (o->sparse_eps > 0.0 && plan->NB >= (int64_t)INT32_MAX)
+    return fail(ctx, ES_EUNSUPPORTED, "sparse levels need (nodes x sources) per batch below 2^31");
   // workspaces (allocated before any capture)
   BatchBuffers bb{};
-  ES_TRY(batch_buffers(ctx, *plan, &bb));
+  ES_TRY(batch_buffers(ctx, *plan, &bb, o->sparse_eps, &block_graphs));
   ES_TRY(lifetime_table(ctx, o->c));
   {
     es_status st;
@@ -833,9 +878,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   // per-call inputs: sources (internal ids) and output pointers, in block order
   std::vector<int32_t> src_int;
   std::vector<double*> outs;
-  std::vector<const es_graph*> block_graphs;
   for (auto& bl : blocks) {
-    block_graphs.push_back(bl.g);
     for (int32_t q : bl.queries) {
       src_int.push_back(bl.g->h_int_of[sources[q]]);
       outs.push_back(s_out[q]);
@@ -883,6 +926,18 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
     float ms = 0;
     ES_CHECK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     s.ms_walk = ms;
+    if (bb.sp.idx) {
+      unsigned long long kept = 0;
+      ES_CHECK_HIP(ctx, hipMemcpy(&kept, bb.sp.cnt + plan->L + 1, sizeof(kept), hipMemcpyDeviceToHost));
+      if (kept > bb.sp.cap)
+        return fail(ctx, ES_EOVERFLOW, "%llu entries above the threshold, capacity %llu", kept,
+                    (unsigned long long)bb.sp.cap);
+      s.level_entries = kept;
+      s.level_bytes = 12ull * kept + 8ull * (uint64_t)plan->NB;
+    } else {
+      s.level_entries = (uint64_t)(plan->L + 1) * (uint64_t)plan->NB;
+      s.level_bytes = 8ull * s.level_entries;
+    }
     *stats = s;
   }
   return ES_OK;

@@ -193,6 +193,15 @@ struct SparseLevels {
 uint64_t sparse_capacity(int32_t n, int64_t m, int32_t L, double theta);
 // internal -> external ids over the whole list
 es_status launch_sparse_ids(es_ctx* ctx, const es_graph* g, int32_t L, const SparseLevels& sp);
+// Over a flat array of n elements (level l of any layout, ids < 2^31): add the
+// level to pi (pi = level when first) and append its entries above theta.
+es_status launch_level_keep(es_ctx* ctx, int64_t n, const double* lvl, bool first, double* pi, const SparseLevels& sp,
+                            int32_t level, int32_t L);
+// s[j] += a D[j] pi^level(j) over the stored entries of one level.
+es_status launch_level_scatter(es_ctx* ctx, int64_t n, const SparseLevels& sp, int32_t level, const double* D,
+                               double a, double* s);
+es_status launch_fill(es_ctx* ctx, int64_t count, unsigned long long* p);
+es_status launch_fill(es_ctx* ctx, int64_t count, double* p);
 
 // launchers (enqueue on ctx->stream)
 // Forward levels.  sp == NULL: levels holds L + 1 dense slots (pi^l in slot l).

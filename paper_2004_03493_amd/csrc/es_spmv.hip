@@ -250,7 +250,7 @@ constexpr int kKeepThreads = 256;
 constexpr int kKeepPer = 16;
 constexpr int kKeepRows = kKeepThreads * kKeepPer;
 
-__global__ __launch_bounds__(kKeepThreads) void level_keep_kernel(int32_t n, const double* __restrict__ lvl,
+__global__ __launch_bounds__(kKeepThreads) void level_keep_kernel(int64_t n, const double* __restrict__ lvl,
                                                                   double theta, int first, double* __restrict__ pi,
                                                                   int32_t* __restrict__ sp_idx,
                                                                   double* __restrict__ sp_val, uint64_t cap,
@@ -361,6 +361,34 @@ int scatter_blocks(uint64_t count) {
 }
 
 }  // namespace
+
+es_status launch_level_keep(es_ctx* ctx, int64_t n, const double* lvl, bool first, double* pi, const SparseLevels& sp,
+                            int32_t level, int32_t L) {
+  level_keep_kernel<<<ceil_div(n, kKeepRows), kKeepThreads, 0, ctx->stream>>>(
+      n, lvl, sp.theta, first ? 1 : 0, pi, sp.idx, sp.val, sp.cap, sp.cnt + level, sp.cnt + L + 1);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status launch_level_scatter(es_ctx* ctx, int64_t n, const SparseLevels& sp, int32_t level, const double* D,
+                               double a, double* s) {
+  level_scatter_kernel<<<scatter_blocks(std::min<uint64_t>(sp.cap, (uint64_t)n)), 256, 0, ctx->stream>>>(
+      level, sp.cnt, sp.cap, sp.idx, sp.val, D, a, s);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status launch_fill(es_ctx* ctx, int64_t count, unsigned long long* p) {
+  if (count > 0) fill_u64_kernel<<<ceil_div(count, 256), 256, 0, ctx->stream>>>(count, p);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
+
+es_status launch_fill(es_ctx* ctx, int64_t count, double* p) {
+  if (count > 0) fill_f64_kernel<<<ceil_div(count, 256), 256, 0, ctx->stream>>>(count, p);
+  ES_CHECK_HIP(ctx, hipGetLastError());
+  return ES_OK;
+}
 
 uint64_t sparse_capacity(int32_t n, int64_t m, int32_t L, double theta) {
   const double dense = (double)(L + 1) * (double)n;

@@ -134,6 +134,47 @@ def test_batch_hip_graph_replays(es, ctx, graphs):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("eps_s", [1e-4, 1e-2])
+def test_batch_sparse_levels_equal_single_source(es, ctx, graphs, eps_s):
+    """Sparse linearization in a batch: every source keeps the entries its own
+    single-source query keeps, so s equals the single-source sparse answer
+    (summation order aside) and the oracle's within 1e-9."""
+    g, og = graphs[1]
+    srcs = pick(og, 10, 4)
+    opts = es.make_opts(C, 1e-4, 31, 1e-3, sparse_eps=eps_s)
+    outs, st = run_batch(es, ctx, [g], [0] * len(srcs), srcs, opts)
+    kept = 0
+    for u, s in zip(srcs, outs):
+        ref, st1 = single(es, ctx, g, u, opts)
+        kept += st1.level_entries
+        assert np.abs(s - ref).max() <= 1e-13
+    q = ox.query(og, srcs[0], C, 1e-4, 31, 1e-3, sparse_eps=eps_s)
+    assert np.abs(outs[0] - q["s"]).max() <= 1e-9
+    assert st.level_entries == kept
+    assert st.level_bytes == 12 * kept + 8 * g.n * len(srcs)
+    say(f"  eps_s={eps_s:g}: {kept} entries kept for {len(srcs)} sources "
+        f"({st.level_bytes / 1e6:.1f} MB vs {8 * (st.L + 1) * g.n * len(srcs) / 1e6:.1f} MB dense)")
+
+
+def test_batch_sparse_uneven_and_hip_graph(es, ctx, graphs):
+    """Sparse levels over uneven graphs in one batch, eager and replayed."""
+    gl = [graphs[0][0], graphs[2][0]]
+    srcs = pick(graphs[0][1], 5, 6) + pick(graphs[2][1], 3, 7)
+    goq = [0] * 5 + [1] * 3
+    opts = es.make_opts(C, 1e-4, 13, 1e-2, sparse_eps=1e-3)
+    eager, st_e = run_batch(es, ctx, gl, goq, srcs, opts, autotune=False)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        graph, st_g = run_batch(es, ctx, gl, goq, srcs, opts, autotune=False, use_hip_graph=True)
+        assert st_g.level_entries == st_e.level_entries
+        for a, b in zip(eager, graph):
+            assert np.array_equal(a, b)
+    for gi, u, s in zip(goq, srcs, eager):
+        ref, _ = single(es, ctx, gl[gi], u, opts)
+        assert np.abs(s - ref).max() <= 1e-13
+
+
 def test_batch_autotune_records_choice(es, ctx, graphs):
     g, og = graphs[2]
     srcs = pick(og, 20, 4)
@@ -153,3 +194,6 @@ def test_batch_argument_errors(es, ctx, graphs):
         es.es_batch(ctx, [g], [0], [g.n], opts, out)
     with pytest.raises(es.EsError):
         es.es_batch(ctx, [g], [0], [0], opts, out, force_width=12)
+    bad = es.make_opts(C, 1e-4, 1, 1e-3, sparse_eps=1.5)
+    with pytest.raises(es.EsError):
+        es.es_batch(ctx, [g], [0], [0], bad, out)

@@ -239,8 +239,8 @@ def test_sparse_argument_errors(es, ctx):
         es.es_forward_sparse(ctx, g, g.n, C, 5, 1e-3, idx, val)
     with pytest.raises(es.EsError):
         es.es_sparse_capacity(10, 10, 5, C, 0.0)
-    # batches keep dense levels
+    # batches check the option too
     sb = torch.empty(g.n, dtype=torch.float64, device="cuda")
     with pytest.raises(es.EsError) as e:
-        es.es_batch(ctx, [g], [0], [0], es.make_opts(C, 1e-3, 1, 1e-2, sparse_eps=1e-3), [sb])
-    assert e.value.args[0].endswith(f"(status {es.ES_EUNSUPPORTED})")
+        es.es_batch(ctx, [g], [0], [0], es.make_opts(C, 1e-3, 1, 1e-2, sparse_eps=-1.0), [sb])
+    assert e.value.args[0].endswith(f"(status {es.ES_EINVAL})")
