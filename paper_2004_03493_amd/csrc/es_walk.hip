@@ -238,9 +238,18 @@ __global__ void zero_totals_kernel(WalkTotals* tot) {
 
 // ---- Philox4x64-10 (Salmon et al., SC 2011) --------------------------------
 
+// 64 x 64 -> 128-bit product from four 32 x 32 -> 64 multiply-adds that share
+// their partial products (no separate low product; each sum fits in 64 bits):
+//   t = a1 b0 + hi(a0 b0),  w = a0 b1 + lo(t),
+//   hi = a1 b1 + hi(t) + hi(w),  lo = lo(w) 2^32 + lo(a0 b0).
 __device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
-  lo = a * b;
-  hi = __umul64hi(a, b);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a1 * b0 + (p00 >> 32);
+  const uint64_t w = (uint64_t)a0 * b1 + (uint32_t)t;
+  hi = (uint64_t)a1 * b1 + ((t >> 32) + (w >> 32));
+  lo = (w << 32) | (uint32_t)p00;
 }
 
 struct Words {
