@@ -8,6 +8,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def pytest_sessionstart(session):
+    # tests load what is built; in a tree where nothing is built yet, build it once
+    lib = os.path.join(ROOT, "paper_2004_03493_amd", "libexactsim.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C ABI on cuda:0)")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
