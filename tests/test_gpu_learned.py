@@ -235,6 +235,36 @@ def test_learned_pairs_at_equal_error(es, ctx, trained, cl2k):
     assert p_eq > 1.5 * p_l
 
 
+def test_learned_with_local_exploitation(es, ctx, trained, cl2k):
+    """The learned allocation combined with Algorithm 3 (reduced): the budget
+    network sets R(k), the exact levels then cut it to R'(k).  All four
+    combinations against the Power Method at the same r_scale."""
+    w, _, _ = trained
+    g, og = cl2k
+    S = sr.power_method(og, C, 60)
+    es.es_mlp_load(ctx, w)
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eps, r_scale = 1e-4, 1e-3
+    variants = [("pi2", es.ES_ALLOC_PI2, es.ES_LDE_OFF), ("learned", es.ES_ALLOC_LEARNED, es.ES_LDE_OFF),
+                ("pi2 + Alg. 3 reduced", es.ES_ALLOC_PI2, es.ES_LDE_REDUCED),
+                ("learned + Alg. 3 reduced", es.ES_ALLOC_LEARNED, es.ES_LDE_REDUCED)]
+    res = {}
+    for label, alloc, lde in variants:
+        errs, pairs = [], 0
+        for u in (0, 5, 50, 300):
+            for seed in range(6):
+                st = es.es_single_source(ctx, g, u, es.make_opts(C, eps, 900 + seed, r_scale, alloc=alloc, lde=lde), s)
+                errs.append(sr.max_error(s.cpu().numpy(), S[:, u]))
+                pairs += st.pairs
+        res[label] = (float(np.mean(errs)), float(np.max(errs)), pairs)
+        say(f"  {label:26s} MaxError mean {res[label][0]:.3e} max {res[label][1]:.3e} pairs {pairs:.4g}")
+    for label, (mean_e, max_e, _) in res.items():
+        assert max_e <= eps, label
+    # the reduced sample count needs fewer pairs under either allocation
+    assert res["learned + Alg. 3 reduced"][2] < 0.8 * res["learned"][2]
+    assert res["pi2 + Alg. 3 reduced"][2] < 0.8 * res["pi2"][2]
+
+
 def test_learned_predictions_cached_per_network(es, ctx, trained, cl2k):
     """The predicted variances are cached in the graph per loaded network and
     decay: repeated queries agree bit for bit, other weights change the
