@@ -301,15 +301,19 @@ def learned_main(args):
             log(f"# {name} step {i}: pairs={stats[-1].pairs} walk {stats[-1].ms_walk:.1f} ms")
         timed[name] = (time.perf_counter() - t, stats)
     # accuracy at equal total pairs against a larger-budget pi^2 run
+    # (MaxError, and Precision@k of the top-k sets as in Section 4)
     ref = torch.empty(g.n, dtype=torch.float64, device="cuda")
     acc = {name: [] for name, *_ in variants}
+    prec = {name: [] for name, *_ in variants}
     pairs = {name: 0 for name, *_ in variants}
     for u in ([] if args.no_accuracy else sources[:4]):
         query(u, es.ES_ALLOC_PI2, wl.seed_walk + 1000, args.r_scale * args.ref_factor, ref)
+        ref_top = set(idx.cpu().tolist())  # query() leaves the top-k of its output in idx
         for seed in (wl.seed_walk + 1, wl.seed_walk + 2):
             for name, alloc, lde, sp_eps in variants:
                 st = query(u, alloc, seed, args.r_scale, s, lde, sp_eps)
                 acc[name].append(float((s - ref).abs().max()))
+                prec[name].append(len(ref_top & set(idx.cpu().tolist())) / args.topk)
                 pairs[name] += st.pairs
         log(f"# accuracy u={u}: " + " ".join(f"{k} {v[-2:]}" for k, v in acc.items()))
     L = timed["pi2"][1][0].L
@@ -367,6 +371,7 @@ def learned_main(args):
             "pairs_lde_reduced": int(pairs["pi2_lde_reduced"]),
             "max_error_pi2_sparse": acc["pi2_sparse"],
             "max_error_pi2_lde_reduced_sparse": acc["pi2_lde_reduced_sparse"],
+            "precision_at_k_mean": {name: (float(np.mean(v)) if v else None) for name, v in prec.items()},
         },
         "projected_full_budget_s_per_query": float(pl["pairs_per_query_mean"] / args.r_scale / pl["walk_pairs_per_s"]),
     }
