@@ -170,11 +170,11 @@ def test_rmat1m_single_source_stages(es, ctx, rmat1m, which):
     assert torch.equal(s_q, s_st)
 
 
-def _batch_vs_single(es, ctx, graphs, goq, sources, eps, c, seed):
-    opts = es.make_opts(c, eps, seed, BATCH_R_SCALE)
+def _batch_vs_single(es, ctx, graphs, goq, sources, eps, c, seed, sparse_eps=0.0):
+    opts = es.make_opts(c, eps, seed, BATCH_R_SCALE, sparse_eps=sparse_eps)
     outs = [torch.empty(graphs[gi].n, dtype=torch.float64, device="cuda") for gi in goq]
     st = es.es_batch(ctx, graphs, goq, sources, opts, outs, use_hip_graph=True)
-    say(f"  batch of {len(sources)}: {st.pairs} pairs")
+    say(f"  batch of {len(sources)}: {st.pairs} pairs, {st.level_bytes / 1e9:.2f} GB of levels")
     one = torch.empty(max(g.n for g in graphs), dtype=torch.float64, device="cuda")
     worst = 0.0
     for q, (gi, u) in enumerate(zip(goq, sources)):
@@ -185,13 +185,16 @@ def _batch_vs_single(es, ctx, graphs, goq, sources, eps, c, seed):
     assert worst <= BATCH_TOL
 
 
-def test_rmat4m8_block64_equals_single_source(es, ctx):
+@pytest.mark.parametrize("sparse_eps", [0.0, 1e-6])
+def test_rmat4m8_block64_equals_single_source(es, ctx, sparse_eps):
+    """Dense levels, and sparse linearization at eps_s = eps (every source keeps
+    exactly the entries its single-source query keeps)."""
     wl = workloads.RMAT_4M8
     say(f"[graph {wl.name}]")
     src, dst = wl.graph()
     g = es.Graph(ctx, wl.n, src, dst)
     sources = [int(x) for x in wl.sources(dst)]
-    _batch_vs_single(es, ctx, [g], [0] * len(sources), sources, wl.eps, wl.c, wl.seed_walk)
+    _batch_vs_single(es, ctx, [g], [0] * len(sources), sources, wl.eps, wl.c, wl.seed_walk, sparse_eps)
 
 
 def test_uneven_twelve_graphs_equal_single_source(es, ctx):
