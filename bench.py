@@ -43,6 +43,7 @@ OPS_PER_PHILOX_BLOCK = 10 * (2 * (4 + 2) + 8)
 OPS_PER_WALK_STEP = 12
 
 WALK_SOURCE = os.path.join(ROOT, "paper_2004_03493_amd", "csrc", "es_walk.hip")
+SPMV_SOURCE = os.path.join(ROOT, "paper_2004_03493_amd", "csrc", "es_spmv.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "walk_pairs_kernel_rmat_n1048576_counters.md")
 
 
@@ -92,6 +93,20 @@ def measured_traffic():
     if not h or not b or h.group(1) != source_hash(WALK_SOURCE):
         return None
     return float(b.group(1))
+
+
+def measured_spmv_traffic():
+    """HBM-side bytes per forward-level launch of the level SpMV on the R-MAT
+    2^20 workload from the committed counter summary, or None if it is missing
+    or was taken on a different SpMV source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    h = re.search(r"spmv_source_sha256_16:\s*([0-9a-f]+)", text)
+    row = re.search(r"\|\s*void spmv_pull_kernel<long, FwdGather, FwdEpi>\s*\|[^|]*\|[^|]*\|[^|]*\|\s*([0-9.eE+]+)\s*\|", text)
+    if not h or not row or h.group(1) != source_hash(SPMV_SOURCE):
+        return None
+    return float(row.group(1))
 
 
 def cpu_baseline(wl, src, dst, u, r_scale, sample_pairs):
@@ -590,6 +605,9 @@ def main():
             "achieved": fwd_bytes / float(fwd_s.mean()) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": fwd_bytes / float(fwd_s.mean()) / 1e9 / PEAK_HBM_GBS,
             "backward_achieved": back_bytes / float(back_s.mean()) / 1e9,
+            # HBM-side bytes of one forward level (counters) next to its algorithmic 4m + 28n
+            "traffic": measured_spmv_traffic(),
+            "algorithmic_bytes_per_level": fwd_bytes / L,
         },
         "walk_pairs_per_s": walk_rate,
         "joint_steps_per_s": float(sum(x["walk_steps"] for x in stats) / walk_s.sum()),
