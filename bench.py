@@ -613,6 +613,7 @@ def main():
         "joint_steps_per_s": float(sum(x["walk_steps"] for x in stats) / walk_s.sum()),
         "philox_blocks_per_s": float(sum(x["philox_blocks"] for x in stats) / walk_s.sum()),
         "pairs_per_query_mean": float(pairs.mean()),
+        "device_workspace_bytes": int(max(x["workspace_bytes"] for x in stats)),
         "ms_forward": float(fwd_s.mean() * 1e3),
         "ms_walk": float(walk_s.mean() * 1e3),
         "ms_backward": float(back_s.mean() * 1e3),

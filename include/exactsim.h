@@ -122,6 +122,8 @@ typedef struct {
                              /*   (L+1) n dense, the kept ones with sparse_eps > 0  */
   uint64_t level_bytes;      /* device bytes holding the levels: 8 (L+1) n dense;   */
                              /*   12 per kept entry plus the dense working slots    */
+  uint64_t workspace_bytes;  /* device bytes the context's workspaces hold after the */
+                             /*   call (they grow on demand and are kept)           */
 } es_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("ms_budget", ctypes.c_float), ("ms_walk", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("ms_backward", ctypes.c_float), ("lde_source_level", ctypes.c_int32),
                 ("lde_source_zsum", ctypes.c_double), ("level_entries", ctypes.c_uint64),
-                ("level_bytes", ctypes.c_uint64)]
+                ("level_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

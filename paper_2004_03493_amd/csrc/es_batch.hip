@@ -938,6 +938,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
       s.level_entries = (uint64_t)(plan->L + 1) * (uint64_t)plan->NB;
       s.level_bytes = 8ull * s.level_entries;
     }
+    s.workspace_bytes = workspace_total(ctx);
     *stats = s;
   }
   return ES_OK;

@@ -43,6 +43,12 @@ es_status hip_fail(es_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, ES_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+uint64_t workspace_total(const es_ctx* ctx) {
+  uint64_t t = 0;
+  for (size_t b : ctx->ws_bytes) t += b;
+  return t;
+}
+
 void* workspace(es_ctx* ctx, int slot, size_t bytes, es_status* st) {
   *st = ES_OK;
   if ((int)ctx->ws.size() <= slot) {

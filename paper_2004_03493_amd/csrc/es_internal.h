@@ -172,6 +172,8 @@ struct WalkTotals {
 es_status fail(es_ctx* ctx, es_status st, const char* fmt, ...);
 es_status hip_fail(es_ctx* ctx, hipError_t e, const char* what);
 void* workspace(es_ctx* ctx, int slot, size_t bytes, es_status* st);
+// device bytes held by the context's workspaces
+uint64_t workspace_total(const es_ctx* ctx);
 
 // lifetime threshold table for decay c, cached on the context
 es_status lifetime_table(es_ctx* ctx, double c);

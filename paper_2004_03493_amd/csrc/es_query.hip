@@ -332,6 +332,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
       s.level_entries = (uint64_t)(L + 1) * (uint64_t)n;
       s.level_bytes = 8ull * s.level_entries;
     }
+    s.workspace_bytes = workspace_total(ctx);
     *stats = s;
   }
   return ES_OK;

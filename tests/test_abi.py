@@ -97,3 +97,36 @@ def test_sparse_capacity_holds_the_pigeonhole_bound():
     for bad in ((0.6, 0.0), (0.6, 1.0), (0.0, 1e-3), (1.0, 1e-3)):
         with pytest.raises(es.EsError):
             es.es_sparse_capacity(100, 100, 5, *bad)
+
+
+def test_binding_structs_match_header_layout():
+    # sizeof and every field offset of the option and statistics structs,
+    # compiled from the header, against the binding's ctypes mirrors
+    import shutil
+    import subprocess
+
+    from paper_2004_03493_amd import binding as es
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"es_query_opts": es.QueryOpts, "es_stats": es.Stats, "es_batch_opts": es.BatchOpts}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "exactsim.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    out = os.path.join(ROOT, "_build", "abi")
+    os.makedirs(out, exist_ok=True)
+    src, exe = os.path.join(out, "layout.c"), os.path.join(out, "layout")
+    with open(src, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    got = {}
+    for line in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            cname, field, val = line.split()
+            got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)

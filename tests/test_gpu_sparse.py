@@ -143,6 +143,7 @@ def test_single_source_against_oracle(es, ctx, name):
         assert st.pairs == st_d.pairs and st.meets == st_d.meets
         assert st.level_entries == kept
         assert st.level_bytes == 12 * kept + 8 * g.n
+        assert st.workspace_bytes >= st.level_bytes
         assert st_d.level_entries == (st_d.L + 1) * g.n
         # Lemma 2: the removed entries lower s by at most eps_s (D^ is in [0, 1])
         assert diff.min() >= -1e-12 and diff.max() <= eps_s
