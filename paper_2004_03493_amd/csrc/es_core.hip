@@ -39,6 +39,9 @@ es_status fail(es_ctx* ctx, es_status st, const char* fmt, ...) {
 }
 
 es_status hip_fail(es_ctx* ctx, hipError_t e, const char* what) {
+  // a failed runtime call also leaves its code as the thread's last error;
+  // consume it, or the next launch check would report it as its own
+  (void)hipGetLastError();
   if (e == hipErrorOutOfMemory) return fail(ctx, ES_ENOMEM, "%s: %s", what, hipGetErrorString(e));
   return fail(ctx, ES_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }

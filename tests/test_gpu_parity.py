@@ -243,6 +243,28 @@ def test_argument_errors(es, ctx):
     assert e.value.status == es.ES_EINVAL
 
 
+def test_allocation_failure_is_reported_and_recoverable(es, ctx):
+    """A query whose level storage cannot exist (c = 0.99, eps = 1e-300: about
+    6.9e4 levels of 2^20 doubles, 0.58 TB) fails with ES_ENOMEM, and the same
+    context then answers an ordinary query."""
+    n = 1 << 20
+    src, dst = workloads.rmat(n, n, 77)
+    g = es.Graph(ctx, n, src, dst)
+    s = torch.empty(n, dtype=torch.float64, device="cuda")
+    D = torch.ones(n, dtype=torch.float64, device="cuda")  # exact-diagonal mode: no walk budget involved
+    L = es.es_num_levels(0.99, 1e-300)
+    assert (L + 1) * n * 8 > 400e9
+    with pytest.raises(es.EsError) as e:
+        es.es_single_source(ctx, g, 0, es.make_opts(0.99, 1e-300, 1, 1.0, d_override=D), s)
+    assert e.value.status == es.ES_ENOMEM
+    g.close()
+    g2, og2 = build_pair(es, ctx, "random_small")
+    s2 = torch.empty(g2.n, dtype=torch.float64, device="cuda")
+    es.es_single_source(ctx, g2, 3, es.make_opts(C, 1e-3, 1, 1e-3), s2)
+    ref = ox.query(og2, 3, C, 1e-3, 1, 1e-3)["s"]
+    assert np.abs(host(s2) - ref).max() <= S_TOL
+
+
 def test_tiny_and_empty_graphs(es, ctx):
     for n, src, dst in ((1, [], []), (3, [], []), (2, [0], [1]), (4, [0, 0, 1], [1, 1, 1])):
         g = es.Graph(ctx, n, np.array(src, dtype=np.int32), np.array(dst, dtype=np.int32))
