@@ -175,6 +175,31 @@ def test_batch_sparse_uneven_and_hip_graph(es, ctx, graphs):
         assert np.abs(s - ref).max() <= 1e-13
 
 
+def test_batch_allocation_failure_is_reported_and_recoverable(es, ctx, graphs):
+    """A batch whose dense levels cannot be allocated (c = 0.99, eps = 1e-140:
+    about 3.2e4 levels of 2^17 x 16 doubles) fails with ES_ENOMEM; the context
+    then runs an ordinary batch."""
+    n = 1 << 17
+    src, dst = workloads.rmat(n, 4 * n, 78)
+    g = es.Graph(ctx, n, src, dst)
+    srcs = [int(x) for x in workloads.pick_sources(n, dst, 16, 3)]
+    L = es.es_num_levels(0.99, 1e-140)
+    assert (L + 1) * n * 16 * 8 > 400e9
+    bad = es.make_opts(0.99, 1e-140, 1, 1e-290)
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in srcs]
+    with pytest.raises(es.EsError) as e:
+        es.es_batch(ctx, [g], [0] * len(srcs), srcs, bad, outs, autotune=False)
+    assert e.value.status == es.ES_ENOMEM
+    g.close()
+    g2, og2 = graphs[2]
+    srcs2 = pick(og2, 4, 9)
+    opts = es.make_opts(C, 1e-4, 9, 1e-2)
+    out2, _ = run_batch(es, ctx, [g2], [0] * 4, srcs2, opts, autotune=False)
+    for u, s2 in zip(srcs2, out2):
+        ref, _ = single(es, ctx, g2, u, opts)
+        assert np.abs(s2 - ref).max() <= 1e-13
+
+
 def test_batch_autotune_records_choice(es, ctx, graphs):
     g, og = graphs[2]
     srcs = pick(og, 20, 4)
