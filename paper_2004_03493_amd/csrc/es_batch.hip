@@ -251,43 +251,64 @@ __global__ void bat_sort_counts(const BEntry* __restrict__ ents, const uint64_t*
 }
 
 // M_b(k) = sum_{j <= #{b' : R_b'(k) < R_b(k)}} H[k][j];  D^ as in the single-source path.
+// One group of B consecutive lanes per node (64 / B nodes per wave, the wave's
+// spare lanes idle): the group scans the node's bucket counts, each source finds
+// its bucket by a fixed-step search over the node's thresholds held one per
+// lane, and reads the inclusive prefix there.  Grid-stride over a grid sized to
+// the resident waves, so the two totals take few atomics.
 __global__ void bat_finish_diag(const BEntry* __restrict__ ents, const uint64_t* __restrict__ Rk,
                                 const uint64_t* __restrict__ T, const uint64_t* __restrict__ H, double c,
                                 int32_t exact_small_din, double* __restrict__ D, unsigned long long* __restrict__ sums) {
   const BEntry E = ents[blockIdx.y];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nb = (int64_t)E.n * E.B;
+  const int lane = threadIdx.x & 63;
+  const int B = E.B;
+  const int gpw = 64 / B;  // nodes per wave
+  const int grp = lane / B;
+  const int b = lane - grp * B;
+  const bool used = grp < gpw;
+  const int64_t nw = ((int64_t)E.n + gpw - 1) / gpw;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
   unsigned long long req = 0, met = 0;
-  if (i < nb) {
-    const int32_t r = (int32_t)(i / E.B);
-    const int64_t row = E.base + (int64_t)r * E.B;
-    const uint64_t R = Rk[E.base + i];
-    double d = 1.0;
-    if (R > 0) {
-      int32_t lo = 0, hi = E.B;  // first threshold >= R
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (T[row + mid] < R) lo = mid + 1;
-        else hi = mid;
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nw; w += stride) {
+    const int64_t r = w * gpw + grp;
+    const bool live = used && r < E.n;
+    const int64_t row = E.base + r * B;
+    uint64_t h = live ? H[row + b] : 0ull;
+    const uint64_t R = live ? Rk[row + b] : 0ull;
+    const uint64_t Tb = live ? T[row + b] : ~0ull;
+    for (int o = 1; o < B; o <<= 1) {  // inclusive scan within the group
+      const uint64_t t = __shfl_up(h, o, 64);
+      if (b >= o) h += t;
+    }
+    // lo = #{j : T[j] < R}, the thresholds ascending (R itself is one of them)
+    int32_t lo = 0;
+    for (int st = 64; st > 0; st >>= 1) {
+      const int32_t j = lo + st - 1;
+      const uint64_t t = __shfl(Tb, grp * B + (j < B ? j : B - 1), 64);
+      if (j < B && t < R) lo += st;
+    }
+    if (lo > B - 1) lo = B - 1;
+    const uint64_t M = __shfl(h, grp * B + lo, 64);
+    if (live) {
+      double d = 1.0;
+      if (R > 0) {
+        d = (double)(R - M) / (double)R;
+        req += R;
+        met += M;
       }
-      uint64_t M = 0;
-      for (int32_t j = 0; j <= lo && j < E.B; ++j) M += H[row + j];
-      d = (double)(R - M) / (double)R;
-      req = R;
-      met = M;
+      if (exact_small_din) {
+        const int32_t din = E.din[r];
+        if (din == 0) d = 1.0;
+        else if (din == 1) d = 1.0 - c;
+      }
+      D[row + b] = d;
     }
-    if (exact_small_din) {
-      const int32_t din = E.din[r];
-      if (din == 0) d = 1.0;
-      else if (din == 1) d = 1.0 - c;
-    }
-    D[E.base + i] = d;
   }
   for (int m = 32; m > 0; m >>= 1) {
     req += __shfl_xor(req, m, 64);
     met += __shfl_xor(met, m, 64);
   }
-  if ((threadIdx.x & 63) == 0 && (req | met)) {
+  if (lane == 0 && (req | met)) {
     atomicAdd(&sums[0], req);
     atomicAdd(&sums[1], met);
   }
@@ -301,13 +322,15 @@ __global__ void bat_back_init(int64_t NB, double a, const double* __restrict__ D
 }
 
 // s_out[q][v] = S[int_of[v]][b] for external node v
+// Source index fastest: a node's B results are one contiguous read, and the
+// writes of neighbouring nodes to each output meet in the same cache lines.
 __global__ void bat_output(const BEntry* __restrict__ ents, const double* __restrict__ S, double* const* __restrict__ outs) {
   const BEntry E = ents[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nb = (int64_t)E.n * E.B;
   if (i >= nb) return;
-  const int32_t b = (int32_t)(i / E.n);
-  const int32_t v = (int32_t)(i - (int64_t)b * E.n);
+  const int32_t v = (int32_t)(i / E.B);
+  const int32_t b = (int32_t)(i - (int64_t)v * E.B);
   outs[E.src_base + b][v] = S[E.base + (int64_t)E.int_of[v] * E.B + b];
 }
 
@@ -547,7 +570,8 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
                                 &tot));
     bat_accumulate_walk<<<1, 1, 0, stream>>>(tot, b.sums);
   }
-  bat_finish_diag<<<egrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.H, p.c, p.small, b.D, b.sums);
+  dim3 dgrid(std::min(p.max_nb_blocks, std::max(1, ctx->num_cus) * 8), p.nent);
+  bat_finish_diag<<<dgrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.H, p.c, p.small, b.D, b.sums);
   // back-accumulation; level L lands in s[L & 1]
   if (sparse) {
     ES_TRY(launch_fill(ctx, NB, b.s[0]));

@@ -98,6 +98,13 @@ __device__ void block_scan2(uint32_t& f, uint64_t& v, uint32_t* tot_f, uint64_t*
   v = vi - v + sv[wave];
 }
 
+// The scans lay the count indices out in descending order: with degree-ordered
+// internal ids, the many low-degree nodes holding a single sample each then
+// open the sample space, and their node switches (a few dependent loads per
+// sample) run alongside the hubs' long runs instead of as the kernel's tail.
+// A pair's draws depend only on (k, r), so the layout does not change results.
+__device__ __forceinline__ int64_t scan_index(int32_t n, int64_t q) { return (int64_t)n - 1 - q; }
+
 // Pass 1: per scan block, the number of nodes with samples and the sample sum.
 __global__ __launch_bounds__(kScanThreads) void scan_count_kernel(int32_t n, const uint64_t* __restrict__ r_begin,
                                                                   const uint64_t* __restrict__ r_end,
@@ -115,9 +122,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_count_kernel(int32_t n, con
   uint32_t f = 0;
   uint64_t v = 0;
   for (int t = 0; t < kScanPer; ++t) {
-    const int64_t k = base + t;
-    if (k < n) {
-      const uint64_t c = sample_count(r_begin, r_end, k);
+    const int64_t q = base + t;
+    if (q < n) {
+      const uint64_t c = sample_count(r_begin, r_end, scan_index(n, q));
       f += c > 0;
       const uint64_t s = v + c;
       if (s < v || (s >> 63)) ovf = 1;
@@ -202,8 +209,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_write_kernel(int32_t n, con
   uint32_t f = 0;
   uint64_t v = 0;
   for (int t = 0; t < kScanPer; ++t) {
-    const int64_t k = base + t;
-    cnt[t] = k < n ? sample_count(r_begin, r_end, k) : 0ull;
+    const int64_t q = base + t;
+    cnt[t] = q < n ? sample_count(r_begin, r_end, scan_index(n, q)) : 0ull;
     f += cnt[t] > 0;
     v += cnt[t];
   }
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_write_kernel(int32_t n, con
   uint64_t off = bsum[blockIdx.x] + v;
   for (int t = 0; t < kScanPer; ++t) {
     if (cnt[t] > 0) {
-      active[pos] = (int32_t)(base + t);
+      active[pos] = (int32_t)scan_index(n, base + t);
       prefix[pos] = off;
       ++pos;
       off += cnt[t];
