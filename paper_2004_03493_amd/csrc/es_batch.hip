@@ -125,6 +125,10 @@ struct BackOp {
   }
 };
 
+// Column ids come in one coalesced load per group (W of them; 64 per wave on a
+// long-row chunk) and are broadcast by lane shuffles, so a row's gathers are
+// issued eight at a time instead of behind their own index loads.  Each group
+// adds its entries in increasing entry order, as a plain loop would.
 template <class Op>
 __global__ __launch_bounds__(kSpmmThreads) void spmm_kernel(const MTile* __restrict__ tiles, int32_t ntiles,
                                                             const BEntry* __restrict__ ents, Op op) {
@@ -137,36 +141,60 @@ __global__ __launch_bounds__(kSpmmThreads) void spmm_kernel(const MTile* __restr
   const int W = E.W;
   const int P = 64 / W;
   const int grp = lane / W, sub = lane - grp * W;
+  const int gl = grp * W;  // the group's first lane
   const bool vb = sub < E.B;
   const int32_t* __restrict__ off = Op::kForward ? E.out_off : E.in_off;
   const int32_t* __restrict__ idx = Op::kForward ? E.out_idx : E.in_idx;
   if (t.row1 >= 0) {
+    // the shuffles read lanes of the reader's own group, which runs the same row
     for (int32_t r = t.row0 + grp; r < t.row1; r += P) {
       const int32_t e0 = off[r], e1 = off[r + 1];
       V acc = 0;
-      int32_t e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        const int32_t c0 = idx[e], c1 = idx[e + 1], c2 = idx[e + 2], c3 = idx[e + 3];
-        if (vb) {
-          const V v0 = op.gather(E, c0, sub), v1 = op.gather(E, c1, sub);
-          const V v2 = op.gather(E, c2, sub), v3 = op.gather(E, c3, sub);
-          acc += v0;
-          acc += v1;
-          acc += v2;
-          acc += v3;
+      for (int32_t eb = e0; eb < e1; eb += W) {
+        const int32_t nc = min(W, e1 - eb);
+        const int32_t col = sub < nc ? idx[eb + sub] : 0;
+        int32_t j = 0;
+        for (; j + 8 <= nc; j += 8) {
+          int32_t c[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) c[u] = __shfl(col, gl + j + u, 64);
+          if (vb) {
+            V v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = op.gather(E, c[u], sub);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+          }
         }
-      }
-      for (; e < e1; ++e) {
-        const int32_t c0 = idx[e];
-        if (vb) acc += op.gather(E, c0, sub);
+        for (; j < nc; ++j) {
+          const int32_t c0 = __shfl(col, gl + j, 64);
+          if (vb) acc += op.gather(E, c0, sub);
+        }
       }
       if (vb) op.epi(E, r, sub, acc);
     }
   } else {
+    // one chunk of a long row: group grp takes the entries grp, grp + P, ...
+    // (wave-uniform trip counts, so every shuffle has all lanes active)
     V acc = 0;
-    for (int32_t e = t.e0 + grp; e < t.e1; e += P) {
-      const int32_t c0 = idx[e];
-      if (vb) acc += op.gather(E, c0, sub);
+    for (int32_t eb = t.e0; eb < t.e1; eb += 64) {
+      const int32_t nb = min(64, t.e1 - eb);
+      const int32_t col = lane < nb ? idx[eb + lane] : 0;
+      for (int32_t j0 = 0; j0 < nb; j0 += 8 * P) {
+        int32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int32_t j = j0 + grp + u * P;
+          c[u] = __shfl(col, j < 64 ? j : 63, 64);
+        }
+        if (vb) {
+          V v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = (j0 + grp + u * P < nb) ? op.gather(E, c[u], sub) : (V)0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+      }
     }
     for (int m = W; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
     if (grp == 0 && vb) op.long_add(E, -t.row1 - 1, sub, acc);
