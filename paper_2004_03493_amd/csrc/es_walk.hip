@@ -382,7 +382,6 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
   int32_t cnt_node = -1;
   uint32_t cnt = 0;
   int32_t cnt_bucket = 0;      // buckets only
-  uint64_t next_thr = 0;       // buckets only: first threshold above the cached bucket
   uint32_t nblocks = 0, nsteps = 0;  // work counters for the roofline, flushed per chunk
   auto flush_meets = [&]() {
     if (cnt) {
@@ -525,7 +524,10 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
               cnt = 1;
             }
           } else {
-            if (pk == cnt_node && r < next_thr && cnt < 0x7fffffffu) {
+            // the cached bucket still holds r while r is below its upper threshold
+            // (read again at each meeting rather than kept in a register)
+            if (pk == cnt_node && cnt < 0x7fffffffu &&
+                (cnt_bucket >= a.B || r < a.T[(int64_t)pk * a.B + cnt_bucket])) {
               ++cnt;
             } else {
               flush_meets();
@@ -537,7 +539,6 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
                 else hi = mid;
               }
               cnt_bucket = lo;
-              next_thr = lo < a.B ? Tk[lo] : ~0ull;
               cnt_node = pk;
               cnt = 1;
             }
