@@ -104,6 +104,39 @@ def test_uneven_multi_graph_batch(es, ctx, graphs):
     assert st.meets == meets
 
 
+def test_batch_degenerate_graphs_and_single_source_blocks(es, ctx, graphs):
+    """Graphs of one node, without edges, with duplicate edges and self-loops,
+    every node a source, next to a one-source block of a larger graph: each
+    answer equals its single-source query and the oracle."""
+    tiny = [(1, [], []), (3, [], []), (2, [0], [1]), (4, [0, 0, 1], [1, 1, 1])]
+    gl, ogs = [], []
+    for n, src, dst in tiny:
+        gl.append(es.Graph(ctx, n, np.array(src, dtype=np.int32), np.array(dst, dtype=np.int32)))
+        ogs.append(OracleGraph(n, src, dst))
+    g2, og2 = graphs[2]
+    gl.append(g2)
+    ogs.append(og2)
+    goq, srcs = [], []
+    for gi, (n, _, _) in enumerate(tiny):
+        goq += [gi] * n
+        srcs += list(range(n))
+    goq.append(len(tiny))
+    srcs.append(pick(og2, 1, 21)[0])
+    opts = es.make_opts(C, 1e-3, 3, 1e-3)
+    say(f"  batch of {len(srcs)} over {len(gl)} graphs, tiny ones included")
+    outs, st = run_batch(es, ctx, gl, goq, srcs, opts, autotune=False)
+    meets = 0
+    for q, (gi, u) in enumerate(zip(goq, srcs)):
+        ref, st1 = single(es, ctx, gl[gi], u, opts)
+        meets += st1.meets
+        assert np.abs(outs[q] - ref).max() <= 1e-13, (gi, u)
+        want = ox.query(ogs[gi], u, C, 1e-3, 3, 1e-3)["s"]
+        assert np.abs(outs[q] - want).max() <= 1e-9, (gi, u)
+    assert st.meets == meets
+    for g in gl[:len(tiny)]:
+        g.close()
+
+
 def test_batch_tilings_agree(es, ctx, graphs):
     g, og = graphs[1]
     srcs = pick(og, 12, 3)
