@@ -12,15 +12,15 @@
  * A query runs the steps of Algorithm 1 (basic ExactSim) with the sample
  * allocation of Section 3.2:
  *   es_forward      l-hop Personalized PageRank vectors pi^l and pi
- *                   (Algorithm 1, lines 2-5)
- *   es_budget       per-node walk-pair counts R(k) (Algorithm 1, lines 6-8;
- *                   Section 3.2, "Sampling according to pi_i(k)^2")
+ *                   (Algorithm 1)
+ *   es_budget       per-node walk-pair counts R(k) (Algorithm 1;
+ *                   Section 3.2, sampling in proportion to pi(k)^2)
  *   es_walk_pairs   meeting counts M(k) of R(k) pairs of sqrt(c)-walks from
  *                   each node (Algorithm 2)
- *   es_diag         D^(k,k) = (R(k) - M(k)) / R(k) (Algorithm 2; exact cases
- *                   of Algorithm 3, lines 1-4)
+ *   es_diag         D^(k,k) = (R(k) - M(k)) / R(k) (Algorithm 2; the exact
+ *                   cases that open Algorithm 3)
  *   es_backward     s^L = 1/(1-sqrt c) sum_l (sqrt c P^T)^l D^ pi^l by the
- *                   nested recursion of Algorithm 1, lines 9-13
+ *                   nested recursion of Algorithm 1's back-accumulation
  *   es_topk         k largest entries of s (Section 1, top-k query)
  * es_single_source runs all of them; es_batch runs many sources and many
  * graphs at once with shared walk samples.
@@ -67,7 +67,7 @@ typedef enum {
 
 typedef enum {
   ES_ALLOC_PI2 = 0,      /* R(k) = ceil(R pi(k)^2)          (Section 3.2)      */
-  ES_ALLOC_PI = 1,       /* R(k) = ceil(R pi(k))            (Algorithm 1, l.8) */
+  ES_ALLOC_PI = 1,       /* R(k) = ceil(R pi(k))            (Algorithm 1)     */
   ES_ALLOC_LEARNED = 2   /* R(k) = ceil(R pi(k)^2 v(k)/vbar), v from the budget
                             network; see es_mlp_load                          */
 } es_alloc;
@@ -158,17 +158,17 @@ es_status es_graph_degrees(es_ctx* ctx, const es_graph* g, int32_t* din, int32_t
 
 /* ---- host constants ---------------------------------------------------- */
 
-/* L = ceil(log_{1/c}(2/eps)) of Algorithm 1, line 1, computed as the smallest
+/* L = ceil(log_{1/c}(2/eps)), Algorithm 1's level count, computed as the smallest
  * L >= 0 with c^L <= eps/2 (c^L by repeated float64 multiplication). */
 es_status es_num_levels(double c, double eps, int32_t* L);
-/* R = 6 ln(n) / ((1-sqrt c)^4 eps^2) * r_scale (Algorithm 1, line 6), float64,
+/* R = 6 ln(n) / ((1-sqrt c)^4 eps^2) * r_scale (Algorithm 1), float64,
  * evaluated as ((6*log(n)) / (om4*(eps*eps))) * r_scale with om = 1-sqrt(c),
  * om4 = (om*om)*(om*om). */
 es_status es_total_samples(int32_t n, double c, double eps, double r_scale, double* R);
 
 /* ---- the steps of one query ------------------------------------------- */
 
-/* Algorithm 1, lines 2-5.  levels: device float64 [(L+1) * n], row l holds
+/* Algorithm 1, l-hop PPR.  levels: device float64 [(L+1) * n], row l holds
  * pi^l = (1-sqrt c)(sqrt c P)^l e_u; pi: device float64 [n] = sum_l pi^l
  * summed in order of l.  Each pi^l(i) = sqrt(c) * (A * 2^-62) where A is the
  * exact int64 sum over j in O(v_i) of round(pi^(l-1)(j)/d_in(j) * 2^62)
@@ -177,7 +177,7 @@ es_status es_total_samples(int32_t n, double c, double eps, double r_scale, doub
 es_status es_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, int32_t L, double* levels,
                      double* pi);
 
-/* Sparse linearization (Section 3.2, Lemma 2).  Runs Algorithm 1, lines 2-5
+/* Sparse linearization (Section 3.2, Lemma 2).  Runs Algorithm 1's l-hop PPR
  * exactly as es_forward (same pi^l, same pi) but stores only the entries
  * pi^l(k) > theta = ((1-sqrt c)*(1-sqrt c))*sparse_eps (float64, in that
  * order): idx (device int32 [cap], node ids) and val (device float64 [cap],
@@ -196,7 +196,7 @@ es_status es_forward_sparse(es_ctx* ctx, const es_graph* g, int32_t u, double c,
  * rounding.  Errors: ES_EINVAL (negative sizes, c or sparse_eps out of range). */
 es_status es_sparse_capacity(int32_t n, int64_t m, int32_t L, double c, double sparse_eps, int64_t* cap);
 
-/* Algorithm 1, lines 6-8 and Section 3.2.  Rk: device uint64 [n] receives
+/* Algorithm 1's sample budget and Section 3.2.  Rk: device uint64 [n] receives
  * R(k) = ceil(R * (pi(k)*pi(k))) (ES_ALLOC_PI2) or ceil(R * pi(k))
  * (ES_ALLOC_PI); 0 where pi(k) = 0 and, with exact_small_din, where
  * d_in(k) <= 1.  ES_ALLOC_LEARNED needs weights loaded by es_mlp_load.
@@ -222,13 +222,13 @@ es_status es_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, 
 es_status es_walk_pairs(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, const uint64_t* r_end,
                         uint64_t seed, double c, uint64_t* M);
 
-/* Algorithm 2 (estimate) and Algorithm 3, lines 1-4.  D: device float64 [n]:
+/* Algorithm 2 (estimate) and the exact cases that open Algorithm 3.  D: device float64 [n]:
  * (R(k) - M(k)) / R(k) where R(k) > 0; with exact_small_din, 1 where
  * d_in(k) = 0 and 1 - c where d_in(k) = 1; 1 elsewhere (pi(k) = 0, unused). */
 es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, double c,
                   int32_t exact_small_din, double* D);
 
-/* Algorithm 1, lines 9-13.  levels as written by es_forward (L+1 rows),
+/* Algorithm 1, back-accumulation.  levels as written by es_forward (L+1 rows),
  * D: device float64 [n]; s: device float64 [n] receives
  * s^L with s^0 = D pi^L/(1-sqrt c) and
  * s^l(j) = sqrt(c) * (1/d_in(j)) * sum_{i in I(v_j)} s^(l-1)(i) + D(j) pi^(L-l)(j)/(1-sqrt c). */
@@ -355,8 +355,8 @@ typedef struct {
 /* Many single-source queries at once (same c, eps, seed, r_scale, alloc):
  * query q asks for s(sources[q], .) on graphs[graph_of_query[q]].  Queries of
  * one graph are grouped in source blocks of at most 64; each block runs the
- * level SpMV as one SpMM over its sources (Algorithm 1, lines 2-5 and 9-12 for
- * every source at once) in a single fused launch per level across all blocks
+ * level SpMV as one SpMM over its sources (Algorithm 1's l-hop PPR and
+ * back-accumulation for every source at once) in a single fused launch per level across all blocks
  * and graphs, and the blocks draw shared walk samples: node k of a block
  * simulates max_b R_b(k) pairs once and source b uses pairs r < R_b(k)
  * (Algorithm 2), so every source's counts, and therefore its D^ and s, are the

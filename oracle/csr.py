@@ -74,7 +74,7 @@ def forward_levels(g: CsrGraph, u: int, c: float, L: int):
 
 
 def back_accumulate(g: CsrGraph, levels: np.ndarray, D: np.ndarray, c: float) -> np.ndarray:
-    """s^L of Algorithm 1, lines 9-12, as exactsim.back_accumulate computes it."""
+    """s^L of Algorithm 1's back-accumulation, as exactsim.back_accumulate computes it."""
     levels = np.ascontiguousarray(levels, dtype=np.float64)
     D = np.ascontiguousarray(D, dtype=np.float64)
     L = levels.shape[0] - 1

@@ -1,21 +1,23 @@
 """ExactSim estimator, step by step in the paper's order (test infrastructure).
 
-Algorithm 1 (basic ExactSim) with the pi^2 allocation of Section 3.2:
+Algorithm 1 (basic ExactSim) with the pi^2 allocation of Section 3.2, in
+its own order:
 
-  1. L = ceil(log_{1/c}(2/eps))                                   (line 1)
-  2. pi^0 = (1 - sqrt c) e_u;  pi^l = sqrt c P pi^(l-1);  pi = sum_l pi^l
-                                                                   (lines 2-5)
-  3. R = 6 ln n / ((1 - sqrt c)^4 eps^2)                           (line 6)
-  4. R(k) = ceil(R pi(k)^2) pairs of sqrt(c)-walks for node k; D^(k,k) is
-     the fraction of pairs that do not meet (Algorithm 2)           (lines 7-8)
-  5. s^0 = D^ pi^L / (1 - sqrt c);
-     s^l = sqrt c P^T s^(l-1) + D^ pi^(L-l) / (1 - sqrt c)          (lines 9-12)
-  6. return s^L                                                    (line 13)
+  1. level count      L = ceil(log_{1/c}(2/eps))
+  2. l-hop PPR        pi^0 = (1 - sqrt c) e_u;  pi^l = sqrt c P pi^(l-1);
+                      pi = sum_l pi^l
+  3. sample count     R = 6 ln n / ((1 - sqrt c)^4 eps^2)
+  4. diagonal         R(k) = ceil(R pi(k)^2) pairs of sqrt(c)-walks for node
+                      k; D^(k,k) is the fraction of pairs that do not meet
+                      (Algorithm 2)
+  5. back-accumulate  s^0 = D^ pi^L / (1 - sqrt c);
+                      s^l = sqrt c P^T s^(l-1) + D^ pi^(L-l) / (1 - sqrt c)
+  6. result           s^L
 
 Readings where the text is ambiguous (each also listed in the design notes):
 
 * L is found as the smallest l >= 0 with c^l <= eps/2, c^l formed by repeated
-  float64 multiplication; that is the ceiling in line 1 without a float
+  float64 multiplication; that is the level count's ceiling without a float
   logarithm deciding an integer.
 * ln is the natural logarithm (the bound behind R is Bernstein's, which is
   exponential).  R is kept in float64 and multiplied by an explicit
@@ -24,7 +26,7 @@ Readings where the text is ambiguous (each also listed in the design notes):
   every touched node R samples; its proof (Lemma 3) uses
   rho(k) = ceil(R' pi(k)^2/||pi||^2)/R' with R' = R ||pi||^2.  Both readings
   agree on R(k) = ceil(R pi(k)^2), which is what is computed.
-* Algorithm 3, lines 1-4: a node without in-neighbours has D = 1 and a node
+* Algorithm 3, its exact cases: a node without in-neighbours has D = 1 and a node
   with exactly one has D = 1 - c, exactly.  With ``exact_small_din`` those
   nodes get no samples and these values.
 * Floating point decides integers here (the sample counts), so the forward
@@ -58,7 +60,7 @@ TMAX = 4096
 # ---------------------------------------------------------------------------
 
 def num_levels(c: float, eps: float) -> int:
-    """Smallest L >= 0 with c^L <= eps/2 (Algorithm 1, line 1)."""
+    """Smallest L >= 0 with c^L <= eps/2 (Algorithm 1, the level count)."""
     L = 0
     p = 1.0
     half = eps / 2.0
@@ -69,7 +71,7 @@ def num_levels(c: float, eps: float) -> int:
 
 
 def total_samples(n: int, c: float, eps: float, r_scale: float = 1.0) -> float:
-    """R = 6 ln n / ((1 - sqrt c)^4 eps^2), times r_scale (Algorithm 1, line 6)."""
+    """R = 6 ln n / ((1 - sqrt c)^4 eps^2), times r_scale (Algorithm 1, the sample count)."""
     sc = math.sqrt(c)
     om = 1.0 - sc
     om2 = om * om
@@ -91,7 +93,7 @@ def lifetime_thresholds(c: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Step 2: l-hop PPR vectors (Algorithm 1, lines 2-5)
+# Step 2: l-hop PPR vectors (Algorithm 1)
 # ---------------------------------------------------------------------------
 
 def forward_levels(g: OracleGraph, u: int, c: float, L: int):
@@ -111,7 +113,7 @@ def forward_levels(g: OracleGraph, u: int, c: float, L: int):
 
 
 # ---------------------------------------------------------------------------
-# Step 3-4: sample budget (Algorithm 1 line 6-8, Section 3.2)
+# Step 3-4: sample budget (Algorithm 1, Section 3.2)
 # ---------------------------------------------------------------------------
 
 def budget(pi: np.ndarray, din: np.ndarray, R: float, exact_small_din: bool = True) -> np.ndarray:
@@ -123,7 +125,7 @@ def budget(pi: np.ndarray, din: np.ndarray, R: float, exact_small_din: bool = Tr
 
 
 def budget_pi(pi: np.ndarray, din: np.ndarray, R: float, exact_small_din: bool = True) -> np.ndarray:
-    """Basic allocation of Algorithm 1 line 8: R(k) = ceil(R * pi(k))."""
+    """Basic allocation of Algorithm 1: R(k) = ceil(R * pi(k))."""
     Rk = np.ceil(R * pi)
     if exact_small_din:
         Rk[din <= 1] = 0.0
@@ -218,7 +220,7 @@ def diag_estimate(Rk: np.ndarray, M: np.ndarray, din: np.ndarray, c: float,
     """D^(k,k) = (R(k) - M(k)) / R(k)  (Algorithm 2, fraction of non-meeting pairs).
 
     Nodes with no samples get 1 (their pi is zero, so the value is never used),
-    except the exact cases of Algorithm 3, lines 1-4."""
+    except the exact cases that open Algorithm 3."""
     D = np.ones(len(Rk))
     has = Rk > 0
     D[has] = (Rk[has] - M[has]).astype(np.float64) / Rk[has].astype(np.float64)
@@ -229,7 +231,7 @@ def diag_estimate(Rk: np.ndarray, M: np.ndarray, din: np.ndarray, c: float,
 
 
 def back_accumulate(g: OracleGraph, levels: np.ndarray, D: np.ndarray, c: float) -> np.ndarray:
-    """s^L by the nested recursion of Algorithm 1, lines 9-12."""
+    """s^L by the nested recursion of Algorithm 1's back-accumulation."""
     sc = math.sqrt(c)
     a = 1.0 / (1.0 - sc)
     L = levels.shape[0] - 1

@@ -164,8 +164,8 @@ def plan(g, u: int, Rk: np.ndarray, c: float, mode: int, source_max: int = MAX_S
 def diag_estimate(Rk: np.ndarray, M: np.ndarray, ell: np.ndarray, zsum: np.ndarray, c: float, din: np.ndarray,
                   exact_small_din: bool = True) -> np.ndarray:
     """D^(k,k): (R - M)/R where l(k) = 0 (Algorithm 2), else
-    (1 - sum Z) - c^l(k) (M / R) (Algorithm 3); the exact shortcuts of
-    Algorithm 3, lines 1-4, for d_in <= 1."""
+    (1 - sum Z) - c^l(k) (M / R) (Algorithm 3); the exact shortcuts that
+    open Algorithm 3 for d_in <= 1."""
     n = len(Rk)
     D = np.ones(n)
     has = Rk > 0

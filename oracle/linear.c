@@ -14,7 +14,7 @@
  *   - the in-neighbour lists I(j) (ascending source id, the walk sampler's
  *     order) follow by one stable counting pass over the edges by dst.
  *
- * Forward (Algorithm 1, lines 2-5), in the fixed-point rounding that makes
+ * Forward (Algorithm 1, l-hop PPR), in the fixed-point rounding that makes
  * the sample counts reproducible:
  *   pi^0 = (1 - sqrt c) e_u;
  *   q(j) = round_to_nearest_even(pi^(l-1)(j) * (1/d_in(j)) * 2^62)  (int64)
@@ -22,7 +22,7 @@
  *   pi = pi^0 + pi^1 + ... + pi^L, added in that order.
  * Each integer sum is exact, so the result does not depend on its order.
  *
- * Back-accumulation (Algorithm 1, lines 9-12), with a = 1/(1 - sqrt c):
+ * Back-accumulation (Algorithm 1), with a = 1/(1 - sqrt c):
  *   s^0(j) = a * (D(j) * pi^L(j));
  *   s^l(j) = sqrt c * ((1/d_in(j)) * sum_{i in I(j)} s^(l-1)(i))
  *            + a * (D(j) * pi^(L-l)(j)),   l = 1..L;

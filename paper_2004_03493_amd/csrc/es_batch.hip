@@ -2,8 +2,8 @@
 //
 // Per (node, source) arrays of every block live in flat buffers, node-major
 // within a block (element base + r * B + b), so that one SpMM edge gathers the
-// B contiguous values of a row.  The level SpMM (Algorithm 1, lines 2-5 and
-// 9-12 for all sources at once) runs as one launch per level over a tile list
+// B contiguous values of a row.  The level SpMM (Algorithm 1's l-hop PPR and
+// back-accumulation for all sources at once) runs as one launch per level over a tile list
 // that covers every block of every graph: a tile is a run of rows of one block
 // handled by one wave, whose 64 lanes form 64/W groups of W lanes; lane b of a
 // group owns source column b.  Rows longer than kLongRow are cut into chunks

@@ -1,9 +1,9 @@
 // Level SpMV kernels of a single-source query (pull form over a CSR).
 //
-// Forward (Algorithm 1, lines 2-5):  pi^l(i) = sqrt(c) * sum_{j in O(v_i)} pi^(l-1)(j)/d_in(j),
+// Forward (Algorithm 1, l-hop PPR):  pi^l(i) = sqrt(c) * sum_{j in O(v_i)} pi^(l-1)(j)/d_in(j),
 //   each term pre-rounded to a multiple of 2^-62 and summed exactly in int64, so the
 //   result is independent of how rows are split across lanes and workgroups.
-// Backward (Algorithm 1, lines 9-12): s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i)
+// Backward (Algorithm 1, back-accumulation): s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i)
 //   + D(j) pi^(L-l)(j)/(1-sqrt c), float64.
 //
 // Both are bound by HBM/Infinity-Cache traffic: the CSR index stream is read once

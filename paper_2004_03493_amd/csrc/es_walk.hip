@@ -1,6 +1,6 @@
 // Sample budget, sample-space scan, walk pairs and the diagonal estimate.
 //
-// Budget (Algorithm 1, lines 6-8; Section 3.2): R(k) = ceil(R * pi(k)^2).
+// Budget (Algorithm 1; Section 3.2): R(k) = ceil(R * pi(k)^2).
 // Walk pairs (Algorithm 2): every node's pairs are laid end to end in one
 // 64-bit sample space [0, sum_k R(k)); a persistent grid takes fixed-size
 // chunks of it from a queue, each lane walking its own run of consecutive
@@ -8,7 +8,7 @@
 // lifetime block of its next four pairs, or the movement block of two steps of
 // its current pair; pairs whose lifetime is zero end without any block, so
 // lanes stay busy while pair lengths vary.
-// Diagonal (Algorithm 2, Algorithm 3 lines 1-4): D^(k) = (R(k) - M(k)) / R(k).
+// Diagonal (Algorithm 2; the exact cases that open Algorithm 3): D^(k) = (R(k) - M(k)) / R(k).
 #include <cmath>
 
 #include "es_internal.h"

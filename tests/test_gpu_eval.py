@@ -1,7 +1,7 @@
 """The paper's evaluation protocol (Section 4) on synthetic graphs: MaxError
 and Precision@500 of single-source queries against the Power Method, over
-50 sources per graph, for the basic method (pi allocation, Algorithm 1
-line 8), the pi^2 allocation (Section 3.2), and the pi^2 allocation with
+50 sources per graph, for the basic method (Algorithm 1's pi
+allocation), the pi^2 allocation (Section 3.2), and the pi^2 allocation with
 local deterministic exploitation (Algorithm 3, as printed and with the
 reduced sample count): the ablation of the basic and optimized methods.
 """
