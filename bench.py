@@ -451,7 +451,7 @@ def main():
     if args.r_scale is None:
         args.r_scale = 1e-7 if args.workload in ("batch64", "uneven") else 1e-5
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "rmat42m":
         return learned_main(args)

@@ -62,7 +62,7 @@ typedef enum {
   ES_ENOMEM = -3,        /* device or host allocation failed */
   ES_EDEVICE = -4,       /* a HIP runtime call failed */
   ES_EOVERFLOW = -5,     /* the total sample count would reach 2^63 */
-  ES_EUNSUPPORTED = -6   /* valid request this build does not implement */
+  ES_EUNSUPPORTED = -6   /* valid request the library does not implement */
 } es_status;
 
 typedef enum {
