@@ -658,8 +658,6 @@ es_status build_batch_plan(es_ctx* ctx, BatchPlan& p, const std::vector<BatchBlo
     E.src_base = src_base;
     int32_t nlf = 0, nlb = 0;
     make_tiles(g->h_out_off, g->n, (int32_t)e, bl.W, bl.G, tf, lf, nlf);
-    const size_t lf_before = lbk.size();
-    (void)lf_before;
     // backward chunks use slots after the forward ones of the same block
     std::vector<MTile> tb_e;
     std::vector<LongRow> lb_e;

@@ -163,7 +163,7 @@ __global__ void budget_weighted_kernel(int32_t n, const double* __restrict__ pi,
 }
 
 __global__ void zero_sums(unsigned long long* S, int n) {
-  if (threadIdx.x < n) S[threadIdx.x] = 0ull;
+  if ((int)threadIdx.x < n) S[threadIdx.x] = 0ull;
 }
 
 // ---- network ------------------------------------------------------------------
