@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import workloads
-from graphs import complete, cycle, hub_graph, random_graph, siblings, three_sources
+from graphs import complete, cycle, hub_graph, random_graph, three_sources
 from oracle import exactsim as ox
 from oracle import simrank as sr
 from oracle.graph import OracleGraph

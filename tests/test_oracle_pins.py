@@ -11,7 +11,6 @@ from fractions import Fraction
 
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import workloads
 from graphs import complete, cycle, golden, random_graph, siblings, three_sources
