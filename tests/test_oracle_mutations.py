@@ -9,9 +9,15 @@ import math
 import numpy as np
 import pytest
 
+import scipy.sparse as sp
+
+import test_oracle_lde as lde_pins
+import test_oracle_mlp as mlp_pins
 import test_oracle_pins as pins
 import test_oracle_sparse as sparse_pins
 from oracle import exactsim as ox
+from oracle import lde
+from oracle import mlp
 from oracle import simrank as sr
 
 
@@ -110,6 +116,71 @@ _orig_diag = ox.diag_estimate
 _orig_exact_diag = sr.exact_diagonal
 _orig_levels = ox.num_levels
 
+def _budget_pi_not_squared(pi, din, R, exact_small_din=True):
+    Rk = np.ceil(R * pi)
+    if exact_small_din:
+        Rk[din <= 1] = 0.0
+    return Rk.astype(np.uint64)
+
+
+def _budget_ignores_small_din(pi, din, R, exact_small_din=True):
+    return np.ceil(R * (pi * pi)).astype(np.uint64)
+
+
+def _topk_ties_to_larger_id(s, u, k):
+    idx = np.arange(len(s))
+    keep = idx != u
+    order = np.lexsort((-idx[keep], -s[keep]))
+    sel = idx[keep][order[:k]]
+    return sel.astype(np.int32), s[sel]
+
+
+def _first_meeting_not_first(g, k, c, L):
+    # meetings at step l, earlier meetings not removed
+    Z = np.zeros(L + 1)
+    for l in range(1, L + 1):
+        pk = lde.transition_rows(g, [k], l)
+        Z[l] = (c ** l) * float(pk.multiply(pk).sum())
+    return Z
+
+
+def _first_meeting_c_not_powered(g, k, c, L):
+    Z = np.zeros(L + 1)
+    Zq = {}
+    for l in range(1, L + 1):
+        pk = lde.transition_rows(g, [k], l)
+        v = c * pk.multiply(pk)
+        for lp in range(1, l):
+            prev = Zq[l - lp]
+            if prev.nnz == 0:
+                continue
+            rows = lde.transition_rows(g, prev.indices, lp)
+            v = v - c * sp.csr_matrix(prev.data[None, :] @ rows.multiply(rows))
+        Zq[l] = sp.csr_matrix(v)
+        Z[l] = float(Zq[l].sum())
+    return Z
+
+
+def _grad_plain_sigmoid_derivative(theta, X, y, w, c):
+    # dp/dz taken as p (1 - p), a plain sigmoid's, instead of p (1 - p/c) for p = c sigmoid(z)
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta)
+    p, (X, a1, h1, a2, h2, z) = mlp.forward(theta, X, c)
+    gz = (w / np.sum(w)) * (1.0 - p) * (-y + (1.0 - y) * p / (1.0 - p))
+    da2 = np.outer(gz, w3) * (a2 > 0)
+    da1 = (da2 @ W2) * (a1 > 0)
+    return mlp.pack(da1.T @ X, da1.sum(0), da2.T @ h1, da2.sum(0), h2.T @ gz, np.sum(gz))
+
+
+def _weighted_budget_unnormalised(pi, din, R, v, exact_small_din=True, floor_ratio=mlp.FLOOR_RATIO):
+    v = np.asarray(v, dtype=np.float32).astype(np.float64)
+    take = pi > 0
+    if exact_small_din:
+        take &= din >= 2
+    Rk = np.ceil((R * (pi * pi)) * v)
+    Rk[~take] = 0.0
+    return Rk.astype(np.uint64)
+
+
 MUTANTS = [
     ("power_method_transposed", sr, "power_method", _power_method_transposed,
      [lambda: pins.test_power_method_matches_direct_solve(0), lambda: pins.test_power_method_matches_direct_solve(1)]),
@@ -137,6 +208,21 @@ MUTANTS = [
      [sparse_pins.test_cycle_closed_form, sparse_pins.test_threshold_value]),
     ("sparsify_shifted_level", ox, "sparsify_levels", _sparsify_shifted,
      [sparse_pins.test_removed_mass_through_ppr_pairs]),
+    ("budget_pi_not_squared", ox, "budget", _budget_pi_not_squared,
+     [pins.test_budget_pi2_and_small_din]),
+    ("budget_ignores_small_din", ox, "budget", _budget_ignores_small_din,
+     [pins.test_budget_pi2_and_small_din]),
+    ("topk_ties_to_larger_id", ox, "topk", _topk_ties_to_larger_id,
+     [pins.test_topk_brute_force]),
+    ("lemma4_meetings_not_first", lde, "first_meeting", _first_meeting_not_first,
+     [lambda: lde_pins.test_lemma4_equals_pair_enumeration("random8a"),
+      lde_pins.test_first_meetings_add_up_to_one_minus_d]),
+    ("lemma4_decay_not_powered", lde, "first_meeting", _first_meeting_c_not_powered,
+     [lambda: lde_pins.test_lemma4_equals_pair_enumeration("random8a")]),
+    ("grad_plain_sigmoid_derivative", mlp, "grad", _grad_plain_sigmoid_derivative,
+     [mlp_pins.test_gradient_matches_central_differences]),
+    ("weighted_budget_unnormalised", mlp, "budget_weighted", _weighted_budget_unnormalised,
+     [mlp_pins.test_weighted_budget_properties]),
 ]
 
 
