@@ -181,6 +181,49 @@ def _weighted_budget_unnormalised(pi, din, R, v, exact_small_din=True, floor_rat
     return Rk.astype(np.uint64)
 
 
+def _lifetime_thresholds_sqrt_c(c):
+    # survival of one walk (sqrt c per step) instead of the pair's (c per step)
+    thr = [0]
+    p = 1.0
+    for _ in range(ox.TMAX):
+        p = p * math.sqrt(c)
+        v = int(p * 18446744073709551616.0)
+        if v == 0:
+            break
+        thr.append(min(v, (1 << 64) - 1))
+    return np.array(thr, dtype=np.uint64)
+
+
+def _total_samples_squared(n, c, eps, r_scale=1.0):
+    om = 1.0 - math.sqrt(c)
+    return 6.0 * math.log(n) / ((om * om) * (eps * eps)) * r_scale
+
+
+def _lde_estimator_without_decay(Rk, M, ell, zsum, c, din, exact_small_din=True):
+    # the non-stop pairs' meeting fraction taken without its weight c^l(k)
+    D = np.ones(len(Rk))
+    has = Rk > 0
+    R = Rk.astype(np.float64)
+    Mf = M.astype(np.float64)
+    basic = has & (ell == 0)
+    D[basic] = (R[basic] - Mf[basic]) / R[basic]
+    tail = has & (ell > 0)
+    D[tail] = (1.0 - zsum[tail]) - Mf[tail] / R[tail]
+    if exact_small_din:
+        D[din == 0] = 1.0
+        D[din == 1] = 1.0 - c
+    return D
+
+
+_orig_features = mlp.features
+
+
+def _features_degrees_swapped(g, c):
+    F = _orig_features(g, c)
+    F[:, [0, 1]] = F[:, [1, 0]]
+    return F
+
+
 MUTANTS = [
     ("power_method_transposed", sr, "power_method", _power_method_transposed,
      [lambda: pins.test_power_method_matches_direct_solve(0), lambda: pins.test_power_method_matches_direct_solve(1)]),
@@ -223,6 +266,14 @@ MUTANTS = [
      [mlp_pins.test_gradient_matches_central_differences]),
     ("weighted_budget_unnormalised", mlp, "budget_weighted", _weighted_budget_unnormalised,
      [mlp_pins.test_weighted_budget_properties]),
+    ("lifetimes_of_one_walk", ox, "lifetime_thresholds", _lifetime_thresholds_sqrt_c,
+     [lambda: pins.test_lifetime_thresholds_match_powers_of_c(0.6)]),
+    ("sample_count_squared_not_fourth", ox, "total_samples", _total_samples_squared,
+     [lambda: pins.test_total_samples_high_precision(2**20, 1e-6)]),
+    ("lde_estimator_without_decay", lde, "diag_estimate", _lde_estimator_without_decay,
+     [lde_pins.test_estimator_formula_and_shortcuts]),
+    ("features_degrees_swapped", mlp, "features", _features_degrees_swapped,
+     [mlp_pins.test_features_on_hand_built_graph]),
 ]
 
 
