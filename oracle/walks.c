@@ -1,8 +1,7 @@
 /*
  * ExactSim oracle: plain C Monte Carlo estimation of the diagonal
- * correction, Algorithm 2 of the paper ("basic method for estimating
- * D(k,k)"): for node k, simulate R(k) pairs of sqrt(c)-walks from v_k and
- * count the pairs that meet.
+ * correction by the basic estimator of Algorithm 2: for node k, simulate
+ * R(k) pairs of sqrt(c)-walks from v_k and count the pairs that meet.
  *
  * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
  * baseline leg of the benchmark may load this library.  It shares no code
