@@ -1,4 +1,5 @@
-"""bench.py outside the GPU: the single-GPU contract and its argument checks."""
+"""bench.py outside the GPU: the single-GPU contract and the gating of its
+measured traffic figures on the kernel sources."""
 import json
 import os
 import subprocess
@@ -15,3 +16,41 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert len(lines) == 1
     msg = json.loads(lines[0])
     assert "one GPU" in msg["error"]
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_fields_follow_the_kernel_sources(tmp_path, monkeypatch):
+    """The roofline traffic figures come from the committed counter summary
+    only while it names the current kernel sources; otherwise they are null."""
+    b = _bench_module()
+    walk = tmp_path / "walk.hip"
+    spmv = tmp_path / "spmv.hip"
+    walk.write_text("// walk kernel v1\n")
+    spmv.write_text("// spmv kernel v1\n")
+    counters = tmp_path / "counters.md"
+    counters.write_text(
+        "| kernel | dispatches | FETCH | WRITE | calibrated bytes / launch | hit |\n"
+        "| void spmv_pull_kernel<long, FwdGather, FwdEpi> | 87 | 1.0 | 2.0 | 1.5e+08 | 0.9 |\n\n"
+        f"    kernel_source_sha256_16: {b.source_hash(str(walk))}\n"
+        "    hbm_bytes_per_launch: 1.25e+12\n"
+        f"    spmv_source_sha256_16: {b.source_hash(str(spmv))}\n")
+    monkeypatch.setattr(b, "COUNTERS", str(counters))
+    monkeypatch.setattr(b, "WALK_SOURCE", str(walk))
+    monkeypatch.setattr(b, "SPMV_SOURCE", str(spmv))
+    assert b.measured_traffic() == 1.25e12
+    assert b.measured_spmv_traffic() == 1.5e8
+    walk.write_text("// walk kernel v2\n")
+    assert b.measured_traffic() is None
+    assert b.measured_spmv_traffic() == 1.5e8
+    spmv.write_text("// spmv kernel v2\n")
+    assert b.measured_spmv_traffic() is None
+    monkeypatch.setattr(b, "COUNTERS", str(tmp_path / "missing.md"))
+    assert b.measured_traffic() is None and b.measured_spmv_traffic() is None
+
