@@ -7,8 +7,9 @@
 // that covers every block of every graph: a tile is a run of rows of one block
 // handled by one wave, whose 64 lanes form 64/W groups of W lanes; lane b of a
 // group owns source column b.  Rows longer than kLongRow are cut into chunks
-// that whole waves sum and add atomically into per-row accumulators, finished
-// by a small launch after the level.  The walk phase shares samples inside a
+// that whole waves sum into one partial slot per chunk; a small launch after
+// the level adds each row's partials in chunk order, so the sums do not
+// depend on which wave finishes first.  The walk phase shares samples inside a
 // block: node k simulates max_b R_b(k) pairs and the meetings are bucketed by
 // the block's sorted per-source counts, so source b sees exactly the meetings of
 // its own pairs r < R_b(k).
@@ -63,8 +64,8 @@ struct MTile {
 struct LongRow {
   int32_t entry;
   int32_t row;
-  int32_t slot;
-  int32_t pad;
+  int32_t slot;  // first partial slot; the row's chunks use slot .. slot + nch - 1
+  int32_t nch;
 };
 
 // ---- level operators ------------------------------------------------------
@@ -75,7 +76,7 @@ struct FwdOp {
   const int64_t* __restrict__ qprev;
   int64_t* __restrict__ qnext;
   double* __restrict__ lvl;
-  long long* __restrict__ acc;  // long rows
+  long long* __restrict__ acc;  // long-row chunk partials
   double sc;
   __device__ __forceinline__ V gather(const BEntry& E, int32_t col, int sub) const {
     return qprev[E.base + (int64_t)col * E.B + sub];
@@ -86,14 +87,11 @@ struct FwdOp {
     lvl[i] = p;
     qnext[i] = (int64_t)rint((p * E.inv_din[r]) * kFix);
   }
-  __device__ __forceinline__ void long_add(const BEntry& E, int32_t slot, int sub, V a) const {
-    atomicAdd((unsigned long long*)&acc[(E.long_base + slot) * kBatchMaxB + sub], (unsigned long long)a);
+  __device__ __forceinline__ void long_put(const BEntry& E, int32_t slot, int sub, V a) const {
+    acc[(E.long_base + slot) * kBatchMaxB + sub] = a;
   }
-  __device__ __forceinline__ V long_take(const BEntry& E, int32_t slot, int sub) const {
-    long long* p = &acc[(E.long_base + slot) * kBatchMaxB + sub];
-    const long long v = *p;
-    *p = 0;
-    return v;
+  __device__ __forceinline__ V long_get(const BEntry& E, int32_t slot, int sub) const {
+    return acc[(E.long_base + slot) * kBatchMaxB + sub];
   }
 };
 
@@ -114,14 +112,11 @@ struct BackOp {
     if (lvl) snext[i] = sc * (E.inv_din[r] * v) + a * (D[i] * lvl[i]);
     else snext[i] = sc * (E.inv_din[r] * v);
   }
-  __device__ __forceinline__ void long_add(const BEntry& E, int32_t slot, int sub, V v) const {
-    atomicAdd(&acc[(E.long_base + slot) * kBatchMaxB + sub], v);
+  __device__ __forceinline__ void long_put(const BEntry& E, int32_t slot, int sub, V v) const {
+    acc[(E.long_base + slot) * kBatchMaxB + sub] = v;
   }
-  __device__ __forceinline__ V long_take(const BEntry& E, int32_t slot, int sub) const {
-    double* p = &acc[(E.long_base + slot) * kBatchMaxB + sub];
-    const double v = *p;
-    *p = 0.0;
-    return v;
+  __device__ __forceinline__ V long_get(const BEntry& E, int32_t slot, int sub) const {
+    return acc[(E.long_base + slot) * kBatchMaxB + sub];
   }
 };
 
@@ -197,7 +192,7 @@ __global__ __launch_bounds__(kSpmmThreads) void spmm_kernel(const MTile* __restr
       }
     }
     for (int m = W; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
-    if (grp == 0 && vb) op.long_add(E, -t.row1 - 1, sub, acc);
+    if (grp == 0 && vb) op.long_put(E, -t.row1 - 1, sub, acc);
   }
 }
 
@@ -211,7 +206,9 @@ __global__ void long_finish_kernel(const LongRow* __restrict__ rows, int32_t nro
   const LongRow L = rows[lr];
   const BEntry E = ents[L.entry];
   if (sub >= E.B) return;
-  op.epi(E, L.row, sub, op.long_take(E, L.slot, sub));
+  typename Op::V v = 0;
+  for (int32_t c = 0; c < L.nch; ++c) v += op.long_get(E, L.slot + c, sub);
+  op.epi(E, L.row, sub, v);
 }
 
 // ---- per-block elementwise kernels (grid.y = block) -------------------------
@@ -385,8 +382,10 @@ struct BatchBlock {
 
 struct BatchPlan {
   BatchPlan* next = nullptr;
-  // key
+  // key: graphs by handle identity (a destroyed graph's address can come
+  // back for a new graph; its uid cannot)
   std::vector<const es_graph*> kg;
+  std::vector<uint64_t> kid;
   std::vector<int32_t> kB, kW, kG;
   int32_t L = 0;
   double c = 0, eps = 0, r_scale = 0;
@@ -444,10 +443,11 @@ void make_tiles(const std::vector<int32_t>& off, int32_t n, int32_t entry, int32
   while (r < n) {
     const int32_t deg = off[r + 1] - off[r];
     if (deg > kLongRow) {
-      const int32_t slot = nlong++;
+      // one partial slot per chunk
+      const int32_t first = nlong;
       for (int32_t e0 = off[r]; e0 < off[r + 1]; e0 += kLongRow)
-        tiles.push_back(MTile{entry, r, -(slot + 1), e0, std::min(e0 + kLongRow, off[r + 1]), r});
-      longs.push_back(LongRow{entry, r, slot, 0});
+        tiles.push_back(MTile{entry, r, -(nlong++ + 1), e0, std::min(e0 + kLongRow, off[r + 1]), r});
+      longs.push_back(LongRow{entry, r, first, nlong - first});
       ++r;
       continue;
     }
@@ -622,7 +622,7 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
 }
 
 bool same_key(const BatchPlan& p, const BatchPlan& q) {
-  return p.kg == q.kg && p.kB == q.kB && p.kW == q.kW && p.kG == q.kG && p.L == q.L && p.c == q.c &&
+  return p.kid == q.kid && p.kg == q.kg && p.kB == q.kB && p.kW == q.kW && p.kG == q.kG && p.L == q.L && p.c == q.c &&
          p.eps == q.eps && p.r_scale == q.r_scale && p.seed == q.seed && p.alloc == q.alloc && p.small == q.small &&
          p.nq == q.nq && p.sparse_eps == q.sparse_eps;
 }
@@ -859,6 +859,7 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   BatchPlan key;
   for (auto& bl : blocks) {
     key.kg.push_back(bl.g);
+    key.kid.push_back(bl.g->uid);
     key.kB.push_back(bl.B);
     key.kW.push_back(bl.W);
     key.kG.push_back(bl.G);

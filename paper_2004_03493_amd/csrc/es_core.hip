@@ -113,7 +113,9 @@ es_status lifetime_table(es_ctx* ctx, double c) {
   }
   const int tmax = t - 1;
   if (!ctx->thr) ES_CHECK_HIP(ctx, hipMalloc(&ctx->thr, sizeof(uint64_t) * (kCap + 1)));
-  ES_CHECK_HIP(ctx, hipMemcpyAsync(ctx->thr, thr.data(), sizeof(uint64_t) * (tmax + 1), hipMemcpyHostToDevice,
+  // the whole table, zeros past tmax: the walk kernels read a fixed number of
+  // leading thresholds whatever c is
+  ES_CHECK_HIP(ctx, hipMemcpyAsync(ctx->thr, thr.data(), sizeof(uint64_t) * (kCap + 1), hipMemcpyHostToDevice,
                                    ctx->stream));
   ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->tmax = tmax;
@@ -556,6 +558,8 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
   if (flags & ES_DEDUP) keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
   es_graph* g = new (std::nothrow) es_graph();
   if (!g) return fail(ctx, ES_ENOMEM, "graph handle");
+  static std::atomic<uint64_t> next_uid{0};
+  g->uid = ++next_uid;
   g->device = ctx->device;
   g->n = n;
   g->m = (int64_t)keys.size();

@@ -67,6 +67,7 @@ struct alignas(16) WalkEntry {
 // level gathers share few cache lines.  Callers only ever see external ids.
 struct es_graph {
   int device = 0;
+  uint64_t uid = 0;            // unique per handle in the process, never reused (keys cached batch plans)
   int32_t n = 0;
   int64_t m = 0;
   int32_t* out_off = nullptr;  // [n+1]  internal rows list O(v) (internal ids, ascending)

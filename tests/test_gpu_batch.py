@@ -167,6 +167,51 @@ def test_batch_hip_graph_replays(es, ctx, graphs):
             assert np.array_equal(a, b)
 
 
+def test_batch_long_rows_bitwise_reproducible(es, ctx, graphs):
+    """R-MAT 2^15 has in- and out-rows longer than the SpMM's long-row cut
+    (1024 entries): their chunk sums are added in chunk order, so eager runs
+    and hipGraph replays give the same bits every time."""
+    g, og = graphs[1]
+    assert og.din.max() > 1024 and og.dout.max() > 1024
+    srcs = pick(og, 8, 17)
+    opts = es.make_opts(C, 1e-4, 19, 1e-2)
+    say(f"  long rows: max in-degree {og.din.max()}, out-degree {og.dout.max()}")
+    base, st0 = run_batch(es, ctx, [g], [0] * 8, srcs, opts, autotune=False, force_width=8, force_rows=8)
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        outs, st = run_batch(es, ctx, [g], [0] * 8, srcs, opts, autotune=False, force_width=8, force_rows=8,
+                             use_hip_graph=rep > 0)
+        assert st.meets == st0.meets
+        for a, b in zip(base, outs):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), rep
+    for u, s in zip(srcs[:2], base):
+        ref, _ = single(es, ctx, g, u, opts)
+        assert np.abs(s - ref).max() <= 1e-13
+
+
+def test_batch_plan_not_reused_for_a_new_graph(es, ctx):
+    """Batch on a graph, destroy it, build another graph of the same size and
+    batch again with the same sources and options (hipGraph on both times):
+    the answer is the new graph's, not a replay of a plan built for the old
+    one (whose handle address may be reused)."""
+    n = 5000
+    srcs = list(range(100, 108))
+    opts = es.make_opts(C, 1e-4, 23, 1e-2)
+    for rep, seed in enumerate((61, 62, 63)):
+        src, dst = workloads.rmat(n, 40_000, seed)
+        g = es.Graph(ctx, n, src, dst)
+        say(f"  graph {rep} (seed {seed})")
+        outs, _ = run_batch(es, ctx, [g], [0] * 8, srcs, opts, autotune=False, use_hip_graph=True)
+        og = OracleGraph(n, src, dst)
+        for u, s in zip(srcs[:3], outs[:3]):
+            ref, _ = single(es, ctx, g, u, opts)
+            assert np.abs(s - ref).max() <= 1e-13, (rep, u)
+            want = ox.query(og, u, C, 1e-4, 23, 1e-2)["s"]
+            assert np.abs(s - want).max() <= 1e-9, (rep, u)
+        g.close()
+
+
 @pytest.mark.parametrize("eps_s", [1e-4, 1e-2])
 def test_batch_sparse_levels_equal_single_source(es, ctx, graphs, eps_s):
     """Sparse linearization in a batch: every source keeps the entries its own

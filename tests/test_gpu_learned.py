@@ -99,6 +99,11 @@ def test_gradient_matches_oracle(es, ctx):
     ref_l = mlp.loss(theta.astype(np.float64), X.astype(np.float64), y, w, C)
     g = grad.cpu().numpy().astype(np.float64)
     assert abs(loss - ref_l) <= 1e-5 * abs(ref_l)
+    # every entry (each weight column and the output bias included), float32
+    # sums against the float64 oracle
+    tol = 1e-5 * np.abs(ref_g).max() + 1e-3 * np.abs(ref_g)
+    bad = np.flatnonzero(np.abs(g - ref_g) > tol)
+    assert bad.size == 0, (bad[:10], g[bad[:10]], ref_g[bad[:10]])
     assert np.linalg.norm(g - ref_g) <= 1e-4 * np.linalg.norm(ref_g)
 
 

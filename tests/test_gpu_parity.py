@@ -119,6 +119,32 @@ def test_budget_walks_diag_bitwise(es, ctx, name):
         assert np.array_equal(host(D).view(np.uint64), ref_D.view(np.uint64))
 
 
+@pytest.mark.parametrize("c", [0.002, 0.05])
+def test_walks_small_decay(es, ctx, c):
+    """A decay whose lifetime table ends within the walk kernel's unrolled
+    thresholds (c^t 2^64 < 1 from t = 7 on at c = 0.002): meeting counts and
+    D^ still equal the oracle's bit for bit."""
+    g, og = build_pair(es, ctx, "rmat_32k")
+    thr = ox.lifetime_thresholds(c)
+    say(f"  c={c} lifetime table ends at t={len(thr) - 1}")
+    rng = np.random.default_rng(9)
+    R = rng.integers(0, 20_000, og.n).astype(np.uint64)
+    R[og.din <= 1] = 0
+    R[int(np.argmax(og.din))] = 2_000_000
+    # a larger decay first leaves its thresholds in the context's table
+    M0 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_walk_pairs(ctx, g, None, u64(R), 3, 0.9, M0)
+    M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
+    es.es_walk_pairs(ctx, g, None, u64(R), 3, c, M)
+    ref_M = ox.walk_counts(og, R, 3, c)
+    assert ref_M.sum() > 0
+    assert np.array_equal(host(M), ref_M)
+    D = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    es.es_diag(ctx, g, u64(R), M, c, 1, D)
+    ref_D = ox.diag_estimate(R, ref_M, og.din, c, True)
+    assert np.array_equal(host(D).view(np.uint64), ref_D.view(np.uint64))
+
+
 def test_walk_ranges_split_and_seed(es, ctx):
     g, og = build_pair(es, ctx, "rmat_32k")
     rng = np.random.default_rng(4)
