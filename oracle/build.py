@@ -1,5 +1,6 @@
-"""Compile the oracle's C parts (test infrastructure): the walk simulator and
-the CSR forward / back-accumulation passes for very large graphs."""
+"""Compile the oracle's C parts (test infrastructure): the walk simulator,
+the CSR forward / back-accumulation passes for very large graphs and the
+edge counter of Algorithm 3's level rule."""
 import os
 import subprocess
 
@@ -8,6 +9,8 @@ SRC = os.path.join(HERE, "walks.c")
 LIB = os.path.join(HERE, "liboraclewalks.so")
 LINEAR_SRC = os.path.join(HERE, "linear.c")
 LINEAR_LIB = os.path.join(HERE, "liboraclelinear.so")
+LDE_SRC = os.path.join(HERE, "lde_count.c")
+LDE_LIB = os.path.join(HERE, "liboraclelde.so")
 
 
 def _compile(src: str, lib: str, force: bool) -> str:
@@ -21,7 +24,12 @@ def _compile(src: str, lib: str, force: bool) -> str:
 
 def build(force: bool = True) -> str:
     _compile(LINEAR_SRC, LINEAR_LIB, force)
+    _compile(LDE_SRC, LDE_LIB, force)
     return _compile(SRC, LIB, force)
+
+
+def build_lde(force: bool = True) -> str:
+    return _compile(LDE_SRC, LDE_LIB, force)
 
 
 def build_linear(force: bool = True) -> str:

@@ -56,3 +56,26 @@ def hub_graph(n, hub_in, hub_out, extra, seed):
     s.append(np.full(hub_out, 2))
     d.append(rng.choice(n, hub_out, replace=False))
     return n, np.concatenate(s), np.concatenate(d)
+
+
+def diamond():
+    # 1 -> 0, 2 -> 0, 3 -> 1, 3 -> 2, 4 -> 3, 0 -> 4: two paths from 0 reach 3
+    return 5, np.array([1, 2, 3, 3, 4, 0]), np.array([0, 0, 1, 2, 3, 4])
+
+
+def fork():
+    # 2 -> 1, 3 -> 1, 1 -> 0, 4 -> 0: nodes 2, 3, 4 have no in-neighbours
+    return 5, np.array([2, 3, 1, 4]), np.array([1, 1, 0, 0])
+
+
+def lde_rounds():
+    """{graph name: (node, [edges counted per round])} from lde_rounds.txt."""
+    out = {}
+    with open(os.path.join(GOLDEN, "lde_rounds.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            parts = line.split()
+            out[parts[0]] = (int(parts[1]), [int(x) for x in parts[2:]])
+    return out
