@@ -37,9 +37,9 @@
  *    return values through host pointers synchronize that stream first.
  *  - One context per host thread; calls on one context must not overlap.
  *  - Node ids are int32 in [0, n); edge and sample counts are 64-bit.
- *  - Results are a pure function of (graph, u, c, eps, seed, r_scale, alloc,
- *    network weights): they do not depend on launch shapes, batch
- *    composition or stream.  pi^l, R(k) and M(k) are bit-exact; s is float64
+ *  - Results are a pure function of the graph, the source, the options of
+ *    es_query_opts and the network weights: they do not depend on launch
+ *    shapes, batch composition or stream.  pi^l, R(k) and M(k) are bit-exact; s is float64
  *    with summation order left to the kernels.
  */
 #ifndef EXACTSIM_H
@@ -92,6 +92,8 @@ typedef struct {
                                 levels dense; in (0, 1) the back-accumulation reads only
                                 the entries pi^l(k) > (1-sqrt c)^2 sparse_eps, which
                                 lowers s(u, j) by at most sparse_eps (es_forward_sparse) */
+  int32_t lde_max_level;     /* Algorithm 3: cap on l(k), 1..ES_LDE_MAX_LEVEL; any other
+                                value runs the printed rule uncapped (es_lde_plan)         */
 } es_query_opts;
 
 typedef enum {
@@ -101,6 +103,7 @@ typedef enum {
 } es_lde_mode;
 
 #define ES_LEARNED_FLOOR 0.5
+#define ES_LDE_MAX_LEVEL 3     /* exact levels this library evaluates (Z_1..Z_3)          */
 
 typedef struct {
   int32_t L;                 /* number of levels                                    */
@@ -238,12 +241,12 @@ es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int3
 /* Whole query: every step above with library-owned workspaces.
  * s_out: device float64 [n].  stats (host, nullable) is filled after a
  * stream synchronization.  With opts->sparse_eps > 0 the forward pass keeps
- * the levels as es_forward_sparse does (Algorithm 3 still reads levels
- * 0..min(3, L) densely), the sample budget uses the full pi, and
+ * the levels as es_forward_sparse does, the sample budget uses the full pi, and
  * s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i), plus
  * D(j) pi^(L-l)(j)/(1-sqrt c) where pi^(L-l)(j) is kept.  Errors: as the
  * steps, plus ES_EINVAL for r_scale <= 0, eps outside (0, 1) or sparse_eps
- * outside [0, 1). */
+ * outside [0, 1), and ES_EUNSUPPORTED when an uncapped Algorithm 3 needs
+ * more than ES_LDE_MAX_LEVEL exact levels (es_lde_plan). */
 es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_query_opts* opts,
                            double* s_out, es_stats* stats);
 
@@ -254,7 +257,7 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
 es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                   double* val_out);
 
-/* ---- local deterministic exploitation (Section 3.3, Algorithm 3) ----------
+/* ---- local deterministic exploitation (Section 3.2, Algorithm 3) ----------
  * Z_l(k) is the probability that two sqrt(c)-walks from v_k first meet at
  * step l (Lemma 4 gives it from the transition probabilities), and
  * D(k,k) = 1 - sum_l Z_l(k).  Algorithm 3 computes Z_1..Z_l(k) exactly and
@@ -262,21 +265,28 @@ es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int3
  * first l(k) steps (sqrt(c)-walks afterwards); M(k) counts those meeting
  * after step l(k) without meeting before:
  *   D^(k,k) = (1 - sum_{l <= l(k)} Z_l(k)) - c^l(k) M(k) / R'(k).
- * l(k) is the largest level whose deterministic work (in-walks of length
- * <= l from v_k, those of length 3 charged at their GPU cost: 2 walk steps
- * each if 8n bytes fit in 128 MiB, else 24) stays within 2 R(k) / sqrt(c);
- * at most min(3, L) for the query source u and 1 for every other node.  R'(k) = R(k)
- * (ES_LDE_AS_PRINTED, smaller variance) or ceil(R(k) c^l(k)) (ES_LDE_REDUCED:
- * every pair weighs at most 1/R(k) and has Bernoulli variance at most 1/4,
- * so the Bernstein bound of Theorem 1 holds as for R(k) plain pairs). */
+ * The level l(k) follows Algorithm 3's edge counter, for every node with
+ * R(k) > 0: round l (l = 0, 1, ...) extends, for l' = 0..l and every node q'
+ * that a walk from v_k reaches in exactly l - l' steps, the transition table
+ * of q' from step l' to l' + 1 and counts one edge per in-neighbour of each
+ * node in that table's support (each node once); l(k) is the round in which
+ * the count reaches 2 R(k) / sqrt(c) (float64: E >= (2 R(k)) / sqrt(c)), or
+ * the first round that counts no edge (then no walk survives another step
+ * and the exact part is all of 1 - D(k,k)).  R'(k) = R(k)
+ * (ES_LDE_AS_PRINTED) or ceil(R(k) c^l(k)) (ES_LDE_REDUCED: every pair weighs
+ * at most 1/R(k) and has Bernoulli variance at most 1/4, so the Bernstein
+ * bound of Theorem 1 holds as for R(k) plain pairs). */
 
-/* levels: device float64 [(L+1) n] from es_forward for source u (only levels
- * 0..min(3, L) are read); Rk: device uint64 [n] (es_budget).  Writes, by
- * external id: ell (device int32 [n]) = l(k), zsum (device float64 [n]) =
- * sum_{l <= l(k)} Z_l(k), Rk_out (device uint64 [n]) = R'(k).  mode:
- * es_lde_mode (ES_LDE_OFF gives l = 0 and R' = R).  Synchronizes once. */
-es_status es_lde_plan(es_ctx* ctx, const es_graph* g, int32_t u, const double* levels, int32_t L, const uint64_t* Rk,
-                      double c, int32_t mode, int32_t* ell, double* zsum, uint64_t* Rk_out);
+/* Rk: device uint64 [n] (es_budget).  Writes, by external id: ell (device
+ * int32 [n]) = l(k) = min(l_printed(k), max_level) for max_level in
+ * 1..ES_LDE_MAX_LEVEL; for any other max_level the printed rule itself.
+ * zsum (device float64 [n]) = sum_{l <= l(k)} Z_l(k), Rk_out (device uint64
+ * [n]) = R'(k).  mode: es_lde_mode (ES_LDE_OFF gives l = 0 and R' = R).
+ * Synchronizes the stream.  Errors: ES_EINVAL (c outside (0, 0.99], mode
+ * outside 0..2), ES_EUNSUPPORTED (uncapped, and some node's rule asks for
+ * more than ES_LDE_MAX_LEVEL levels; the outputs are then undefined). */
+es_status es_lde_plan(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, double c, int32_t mode,
+                      int32_t max_level, int32_t* ell, double* zsum, uint64_t* Rk_out);
 /* Algorithm 3's sampling: es_walk_pairs with the pairs of node k taking
  * ell[k] (device int32 [n], 0..L) non-stop steps first; a meeting at a step
  * t <= ell[k] ends the pair uncounted, the joint lifetime is ell[k] + T. */

@@ -27,6 +27,7 @@ ES_ALLOC_PI2 = 0
 ES_ALLOC_PI = 1
 ES_ALLOC_LEARNED = 2
 ES_LDE_OFF, ES_LDE_AS_PRINTED, ES_LDE_REDUCED = 0, 1, 2
+ES_LDE_MAX_LEVEL = 3
 ES_LEARNED_FLOOR = 0.5  # recommended v_floor_ratio of the learned allocation
 
 ES_DEDUP = 1
@@ -53,7 +54,7 @@ class QueryOpts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("r_scale", ctypes.c_double), ("alloc", ctypes.c_int32), ("exact_small_din", ctypes.c_int32),
                 ("d_override", ctypes.c_void_p), ("v_floor_ratio", ctypes.c_double), ("lde", ctypes.c_int32),
-                ("sparse_eps", ctypes.c_double)]
+                ("sparse_eps", ctypes.c_double), ("lde_max_level", ctypes.c_int32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -119,7 +120,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_mlp_train": [P, P, P, P, i64, dbl, i32, ctypes.c_float, P, P],
         "es_mlp_load": [P, P],
         "es_budget_weighted": [P, P, P, P, dbl, i32, dbl, P],
-        "es_lde_plan": [P, P, i32, P, i32, P, dbl, i32, P, P, P],
+        "es_lde_plan": [P, P, P, dbl, i32, i32, P, P, P],
         "es_walk_pairs_lde": [P, P, P, P, P, u64, dbl, P],
         "es_diag_lde": [P, P, P, P, P, P, dbl, i32, P],
     }
@@ -290,7 +291,7 @@ def es_backward(ctx: Context, g: Graph, levels, L: int, D, c: float, s):
 
 def make_opts(c: float, eps: float, seed: int, r_scale: float = 1.0, alloc: int = ES_ALLOC_PI2,
               exact_small_din: bool = True, d_override=None, v_floor_ratio: float = ES_LEARNED_FLOOR,
-              lde: int = ES_LDE_OFF, sparse_eps: float = 0.0) -> QueryOpts:
+              lde: int = ES_LDE_OFF, sparse_eps: float = 0.0, lde_max_level: int = ES_LDE_MAX_LEVEL) -> QueryOpts:
     o = QueryOpts()
     o.c, o.eps, o.seed, o.r_scale = c, eps, seed, r_scale
     o.alloc, o.exact_small_din = alloc, int(exact_small_din)
@@ -298,6 +299,7 @@ def make_opts(c: float, eps: float, seed: int, r_scale: float = 1.0, alloc: int 
     o.v_floor_ratio = v_floor_ratio
     o.lde = lde
     o.sparse_eps = sparse_eps
+    o.lde_max_level = lde_max_level
     return o
 
 
@@ -394,9 +396,8 @@ def es_budget_weighted(ctx: Context, g: Graph, pi, v, R: float, exact_small_din:
                                              _ptr(Rk, torch.uint64, g.n, "Rk")), ctx)
 
 
-def es_lde_plan(ctx: Context, g: Graph, u: int, levels, L: int, Rk, c: float, mode: int, ell, zsum, Rk_out):
-    _check(load_library().es_lde_plan(ctx.handle, g.handle, u, _ptr(levels, torch.float64, (L + 1) * g.n, "levels"),
-                                      L, _ptr(Rk, torch.uint64, g.n, "Rk"), c, mode,
+def es_lde_plan(ctx: Context, g: Graph, Rk, c: float, mode: int, max_level: int, ell, zsum, Rk_out):
+    _check(load_library().es_lde_plan(ctx.handle, g.handle, _ptr(Rk, torch.uint64, g.n, "Rk"), c, mode, max_level,
                                       _ptr(ell, torch.int32, g.n, "ell"), _ptr(zsum, torch.float64, g.n, "zsum"),
                                       _ptr(Rk_out, torch.uint64, g.n, "Rk_out")), ctx)
 

@@ -629,6 +629,8 @@ es_status es_graph_destroy(es_graph* g) {
   (void)hipFree(g->ext_of);
   (void)hipFree(g->int_of);
   (void)hipFree(g->vhat);
+  (void)hipFree(g->lde_n1);
+  (void)hipFree(g->lde_g);
   free_plan(&g->fwd);
   free_plan(&g->back);
   delete g;

@@ -93,6 +93,10 @@ struct es_graph {
   mutable float* vhat = nullptr;
   mutable uint64_t vhat_net = 0;
   mutable double vhat_c = 0.0;
+  // Algorithm 3's level rule, by internal id (computed on first use):
+  // sum of d_in over I(v), and sum of 1/d_in over I(v)
+  mutable long long* lde_n1 = nullptr;
+  mutable double* lde_g = nullptr;
 };
 
 struct es_ctx {
@@ -151,8 +155,19 @@ enum Slot : int {
   kWsLdeR,
   kWsLdeW,
   kWsLdeMisc,
-  kWsLdeLv,
   kWsLdeRin,
+  kWsLdeCand,
+  kWsLdeStats,
+  kWsLdeEnt0,
+  kWsLdeEnt1,
+  kWsLdeCnt,
+  kWsLdePre,
+  kWsLdeTsum,
+  kWsLdeKeys,
+  kWsLdeVals,
+  kWsLdeReg,
+  kWsLdeSums,
+  kWsLdeRows,
   kWsSpIdx,
   kWsSpVal,
   kWsSpCnt,
@@ -230,17 +245,18 @@ es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,
                       double c, int32_t exact_small_din, double* D);
 
-// Local deterministic exploitation (Algorithm 3), internal order.  lv: forward
-// levels pi^0..pi^L of source u (internal id); Rk: budget.  Writes l(k), the
-// exact part sum_{l <= l(k)} Z_l(k) and the pair counts R'(k); *level_u and
-// *zsum_u (host, nullable) receive the source's values (synchronizes).
+// Local deterministic exploitation (Algorithm 3), internal order.  Rk: budget.
+// Writes l(k) = min(l_printed(k), max_level) (max_level outside 1..3: the
+// printed rule uncapped, ES_EUNSUPPORTED where it needs more than 3 levels),
+// the exact part sum_{l <= l(k)} Z_l(k) and the pair counts R'(k).
+// Synchronizes the stream.
 struct LdeOut {
   int32_t* ell;
   double* zsum;
   uint64_t* Rk2;
 };
-es_status launch_lde(es_ctx* ctx, const es_graph* g, int32_t u, const double* lv, int32_t L, const uint64_t* Rk,
-                     double c, int32_t mode, LdeOut out, int32_t* level_u, double* zsum_u);
+es_status launch_lde(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, double c, int32_t mode, int32_t max_level,
+                     LdeOut out);
 es_status launch_diag_lde(es_ctx* ctx, int32_t n, const uint64_t* Rk, const uint64_t* M, const int32_t* ell,
                           const double* zsum, const int32_t* din, double c, int32_t exact_small_din, double* D);
 // dst[row * n + i] = src[row * n + map[i]] for rows = 0..rows-1

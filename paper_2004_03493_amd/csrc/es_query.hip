@@ -216,15 +216,13 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
   if (!o->d_override && R + (double)n >= 9.2e18)
     return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
   es_status st;
-  // sparse linearization: Algorithm 3 reads levels 0..min(3, L) of the source
-  // densely, so those stay dense next to the working slot
   const bool sparse = o->sparse_eps > 0.0;
   SparseLevels sp{};
   int32_t dense_slots = L + 1;
   if (sparse) {
     const double sc = std::sqrt(o->c);
     sp.theta = (1.0 - sc) * (1.0 - sc) * o->sparse_eps;
-    sp.nkeep = (o->lde && !o->d_override) ? std::min(L, 3) + 1 : 0;
+    sp.nkeep = 0;
     sp.cap = sparse_capacity(n, g->m, L, sp.theta);
     dense_slots = std::min(L + 1, sp.nkeep + 1);
     sp.idx = (int32_t*)workspace(ctx, kWsSpIdx, sizeof(int32_t) * (size_t)sp.cap, &st);
@@ -275,8 +273,11 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
       if (!lo.zsum) return st;
       lo.Rk2 = (uint64_t*)workspace(ctx, kWsLdeR, sizeof(uint64_t) * (size_t)n, &st);
       if (!lo.Rk2) return st;
-      ES_TRY(launch_lde(ctx, g, g->h_int_of[u], levels, L, Rk, o->c, o->lde, lo, &lde_level,
-                        stats ? &lde_zsum : nullptr));
+      ES_TRY(launch_lde(ctx, g, Rk, o->c, o->lde, o->lde_max_level, lo));
+      if (stats) {
+        ES_CHECK_HIP(ctx, hipMemcpy(&lde_level, lo.ell + g->h_int_of[u], 4, hipMemcpyDeviceToHost));
+        ES_CHECK_HIP(ctx, hipMemcpy(&lde_zsum, lo.zsum + g->h_int_of[u], 8, hipMemcpyDeviceToHost));
+      }
       Rwalk = lo.Rk2;
     }
     ctx->ev_walk_begin = ev[2];  // recorded between the sample-space scan and the walk kernel

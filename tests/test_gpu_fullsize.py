@@ -223,20 +223,27 @@ def _lde_full(es, ctx, g, og, u, c, eps, r_scale, seed, ref_pi, lv, L):
     assert np.array_equal(host(Rk), ref_R)
     others = np.arange(g.n) != u
     plans = {}
+    # Lemma 4 on the CPU for the source where the sparse-matrix oracle holds the graph
+    znodes = [u] if hasattr(og, "PT") else []
     for mode in (1, 2):
         ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
         zsum = torch.empty(g.n, dtype=torch.float64, device="cuda")
         R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
-        es.es_lde_plan(ctx, g, u, lv, L, Rk, c, mode, ell, zsum, R2)
-        r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, c, mode, source_max=min(3, L), source_zsum=False)
+        es.es_lde_plan(ctx, g, Rk, c, mode, 3, ell, zsum, R2)
+        r_ell, r_z, r_R2 = lde.plan(og, ref_R, c, mode, max_level=3, zsum_nodes=znodes if mode == 1 else [])
         assert np.array_equal(host(ell), r_ell)
         assert np.array_equal(host(R2), r_R2)
         gz = host(zsum)
-        assert np.array_equal(gz[others].view(np.uint64), r_z[others].view(np.uint64))
-        assert 0.0 < gz[u] < 1.0 or r_ell[u] == 0
+        shallow = r_ell <= 1
+        assert np.array_equal(gz[shallow].view(np.uint64), r_z[shallow].view(np.uint64))
+        deep = np.flatnonzero(r_ell >= 2)
+        assert np.all((gz[deep] > 0.0) & (gz[deep] < 1.0))
+        if mode == 1 and znodes and r_ell[u] >= 2:
+            assert abs(gz[u] - r_z[u]) <= 1e-13, (gz[u], r_z[u])
         plans[mode] = (ell, zsum, R2, r_ell, r_z, r_R2)
     ell, zsum, R2, r_ell, r_z, r_R2 = plans[2]
-    say(f"  l(u)={int(r_ell[u])} zsum(u)={host(zsum)[u]:.6g} pairs {int(r_R2.sum())} (plain {int(ref_R.sum())})")
+    say(f"  l(u)={int(r_ell[u])} zsum(u)={host(zsum)[u]:.6g} pairs {int(r_R2.sum())} (plain {int(ref_R.sum())}); "
+        f"{int((r_ell >= 2).sum())} nodes with l >= 2, {int((r_ell == 3).sum())} with l = 3")
     M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
     es.es_walk_pairs_lde(ctx, g, None, R2, ell, seed, c, M)
     gM = host(M)
@@ -259,6 +266,8 @@ def _lde_full(es, ctx, g, og, u, c, eps, r_scale, seed, ref_pi, lv, L):
         assert host(head)[u] + host(tail)[u] == gM[u]
     D = torch.empty(g.n, dtype=torch.float64, device="cuda")
     es.es_diag_lde(ctx, g, R2, M, ell, zsum, c, True, D)
+    # estimator values where the oracle's exact part is bitwise (l <= 1)
+    light = light[r_ell[light] <= 1]
     ref_D = lde.diag_estimate(r_R2[light], ref_M[light], r_ell[light], r_z[light], c, og.din[light])
     assert np.array_equal(host(D)[light].view(np.uint64), ref_D.view(np.uint64))
     s_st = torch.empty(g.n, dtype=torch.float64, device="cuda")

@@ -1,6 +1,7 @@
-"""GPU local deterministic exploitation (Section 3.3, Algorithm 3, Lemma 4)
-against the oracle: the level plan, the non-stop walk pairs, the estimator,
-whole queries, and accuracy against the Power Method."""
+"""GPU local deterministic exploitation (Section 3.2, Algorithm 3, Lemma 4)
+against the oracle: the level plan (the printed edge-counter rule for every
+sampled node, capped or not), the non-stop walk pairs, the estimator, whole
+queries, and accuracy against the Power Method."""
 import sys
 
 import numpy as np
@@ -8,7 +9,7 @@ import pytest
 import torch
 
 import workloads
-from graphs import hub_graph, random_graph
+from graphs import diamond, fork, hub_graph, random_graph, three_sources
 from oracle import exactsim as ox
 from oracle import lde
 from oracle import simrank as sr
@@ -78,12 +79,30 @@ def stages(es, ctx, g, og, u, eps, r_scale):
     return L, lv, Rk, ref_lv, ref_R
 
 
-def gpu_plan(es, ctx, g, u, lv, L, Rk, mode):
+def gpu_plan(es, ctx, g, Rk, mode, cap=3):
     ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
     zsum = torch.empty(g.n, dtype=torch.float64, device="cuda")
     R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
-    es.es_lde_plan(ctx, g, u, lv, L, Rk, C, mode, ell, zsum, R2)
+    es.es_lde_plan(ctx, g, Rk, C, mode, cap, ell, zsum, R2)
     return ell, zsum, R2
+
+
+def check_plan(og, got, ref_R, mode, cap, u, zmax=40):
+    """GPU plan against the oracle: levels and counts bit for bit, the exact
+    part bit for bit at one level (c/d_in) and within 1e-13 deeper (Lemma 4,
+    on the source and on up to zmax other deep nodes)."""
+    ell, zsum, R2 = (host(t) for t in got)
+    r_ell = lde.plan(og, ref_R, C, mode, max_level=cap, zsum_nodes=[])[0]
+    deep = np.flatnonzero(r_ell >= 2)
+    pick = [int(k) for k in deep if k == u] + [int(k) for k in deep if k != u][:zmax]
+    r_ell, r_z, r_R2 = lde.plan(og, ref_R, C, mode, max_level=cap, zsum_nodes=pick)
+    assert np.array_equal(ell, r_ell)
+    assert np.array_equal(R2, r_R2)
+    shallow = r_ell <= 1
+    assert np.array_equal(zsum[shallow].view(np.uint64), r_z[shallow].view(np.uint64))
+    for k in pick:
+        assert abs(zsum[k] - r_z[k]) <= 1e-13 * max(1.0, abs(r_z[k])), (k, r_ell[k], zsum[k], r_z[k])
+    return r_ell, len(deep)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -93,15 +112,43 @@ def test_plan_matches_oracle(es, ctx, name):
         for r_scale in (1e-6, 1e-3, 1e-1):
             L, lv, Rk, _, ref_R = stages(es, ctx, g, og, u, 1e-4, r_scale)
             for mode in (lde.MODE_OFF, lde.MODE_AS_PRINTED, lde.MODE_REDUCED):
-                ell, zsum, R2 = gpu_plan(es, ctx, g, u, lv, L, Rk, mode)
-                r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, C, mode, source_max=min(3, L))
-                assert np.array_equal(host(ell), r_ell)
-                assert np.array_equal(host(R2), r_R2)
-                gz = host(zsum)
-                others = np.arange(g.n) != u
-                assert np.array_equal(gz[others].view(np.uint64), r_z[others].view(np.uint64))
-                assert abs(gz[u] - r_z[u]) <= 1e-13 * max(1.0, abs(r_z[u]))
-            say(f"  u={u} r_scale={r_scale:g}: l(u)={int(r_ell[u])} zsum(u)={r_z[u]:.6g}")
+                for cap in ((1, 2, 3) if mode == lde.MODE_AS_PRINTED else (3,)):
+                    got = gpu_plan(es, ctx, g, Rk, mode, cap)
+                    r_ell, ndeep = check_plan(og, got, ref_R, mode, cap, u)
+            say(f"  u={u} r_scale={r_scale:g}: l(u)={int(r_ell[u])}, {ndeep} nodes with l >= 2, "
+                f"{int((r_ell == 3).sum())} with l = 3")
+
+
+def test_plan_uncapped(es, ctx):
+    """The printed rule without a cap: where it asks for more than three
+    levels the call is refused; where it stays within three (or the rounds
+    run dry) the plan equals the oracle's."""
+    g, og = pair(es, ctx, "chung_lu_2k")
+    u = int(np.argmax(og.din))
+    for r_scale in (1e-6, 1e-4, 1e-2, 1.0):
+        L, lv, Rk, _, ref_R = stages(es, ctx, g, og, u, 1e-4, r_scale)
+        r4 = lde.plan(og, ref_R, C, lde.MODE_AS_PRINTED, max_level=4, zsum_nodes=[])[0]
+        if r4.max() >= 4:
+            with pytest.raises(es.EsError) as e:
+                gpu_plan(es, ctx, g, Rk, lde.MODE_AS_PRINTED, 0)
+            assert e.value.status == es.ES_EUNSUPPORTED
+            say(f"  r_scale={r_scale:g}: {int((r4 >= 4).sum())} nodes need 4+ levels: refused")
+        else:
+            got = gpu_plan(es, ctx, g, Rk, lde.MODE_AS_PRINTED, 0)
+            check_plan(og, got, ref_R, lde.MODE_AS_PRINTED, 4, u)
+            say(f"  r_scale={r_scale:g}: uncapped plan, l(u)={int(r4[u])}")
+    # graphs whose rounds run dry take their exact level whatever the budget
+    for mk in (fork, three_sources, diamond):
+        n, s_, d_ = mk()
+        g2 = es.Graph(ctx, n, s_, d_)
+        og2 = OracleGraph(n, s_, d_)
+        R = np.zeros(n, dtype=np.uint64)
+        R[0] = 10 ** 12
+        ell, zsum, _ = gpu_plan(es, ctx, g2, dev(R, torch.uint64), lde.MODE_AS_PRINTED, 3)
+        ref = lde.printed_exploitation(og2, 0, C, lde.edge_budget(R, C)[0], cap=3)
+        assert int(host(ell)[0]) == ref[0]
+        assert abs(host(zsum)[0] - sum(ref[1])) <= 1e-15
+        g2.close()
 
 
 @pytest.mark.parametrize("name", ["chung_lu_2k", "rmat_32k", "hubs"])
@@ -151,7 +198,7 @@ def test_single_source_equals_stages_and_oracle(es, ctx, name, mode):
     u = int(np.argmax(og.din))
     eps, r_scale, seed = 1e-4, 1e-3, 77
     L, lv, Rk, ref_lv, ref_R = stages(es, ctx, g, og, u, eps, r_scale)
-    ell, zsum, R2 = gpu_plan(es, ctx, g, u, lv, L, Rk, mode)
+    ell, zsum, R2 = gpu_plan(es, ctx, g, Rk, mode)
     M = torch.empty(g.n, dtype=torch.uint64, device="cuda")
     es.es_walk_pairs_lde(ctx, g, None, R2, ell, seed, C, M)
     D = torch.empty(g.n, dtype=torch.float64, device="cuda")
@@ -164,16 +211,17 @@ def test_single_source_equals_stages_and_oracle(es, ctx, name, mode):
     assert st.pairs == int(host(R2).sum())
     assert st.lde_source_level == int(host(ell)[u])
     # the oracle end to end
-    r_ell, r_z, r_R2 = lde.plan(og, u, ref_R, C, mode, source_max=min(3, L))
+    r_ell, r_z, r_R2 = lde.plan(og, ref_R, C, mode)
     r_M = ox.walk_counts(og, r_R2, seed, C, nonstop=r_ell)
     assert np.array_equal(host(M), r_M)
     r_D = lde.diag_estimate(r_R2, r_M, r_ell, r_z, C, og.din)
     r_s = ox.back_accumulate(og, ref_lv, r_D, C)
     err = np.abs(host(s_q) - r_s).max()
     say(f"  l(u)={st.lde_source_level} zsum(u)={st.lde_source_zsum:.6g} pairs {st.pairs} "
-        f"(plain {int(ref_R.sum())}) max|s - oracle| {err:.1e}")
+        f"(plain {int(ref_R.sum())}) max|s - oracle| {err:.1e}, {int((r_ell >= 2).sum())} nodes with l >= 2")
     assert err <= S_TOL
     assert abs(st.lde_source_zsum - r_z[u]) <= 1e-13
+    assert np.abs(host(zsum) - r_z).max() <= 1e-13
 
 
 def test_accuracy_against_power_method(es, ctx):
@@ -206,14 +254,14 @@ def _oracle_lde_query(og, u, eps, seed, r_scale, mode):
     lv, pi = ox.forward_levels(og, u, C, L)
     R = ox.total_samples(og.n, C, eps, r_scale)
     Rk = ox.budget(pi, og.din, R, True)
-    ell, z, R2 = lde.plan(og, u, Rk, C, mode, source_max=min(3, L))
+    ell, z, R2 = lde.plan(og, Rk, C, mode)
     M = ox.walk_counts(og, R2, seed, C, nonstop=ell)
     return ox.back_accumulate(og, lv, lde.diag_estimate(R2, M, ell, z, C, og.din), C)
 
 
 def test_tiny_graphs_and_small_l(es, ctx):
     """Empty and tiny graphs, sources without in-neighbours, and eps = 0.9
-    (L = 2, so the source gets at most two exact levels)."""
+    (L = 2: the exact levels do not depend on L)."""
     cases = [(1, [], []), (3, [], []), (2, [0], [1]), (4, [0, 0, 1], [1, 1, 1]),
              (5, [1, 2, 3, 4, 2, 3], [0, 0, 0, 0, 1, 1]), (6, [0, 1, 2, 3, 4, 5], [1, 2, 3, 4, 5, 0])]
     for n, src, dst in cases:
@@ -234,16 +282,22 @@ def test_lde_argument_errors(es, ctx):
     with pytest.raises(es.EsError) as e:
         es.es_single_source(ctx, g, 0, es.make_opts(C, 1e-3, 1, 1e-3, lde=3), s)
     assert e.value.status == es.ES_EINVAL
-    L = ox.num_levels(C, 1e-3)
-    lv = torch.zeros((L + 1) * g.n, dtype=torch.float64, device="cuda")
     Rk = torch.zeros(g.n, dtype=torch.uint64, device="cuda")
     ell = torch.empty(g.n, dtype=torch.int32, device="cuda")
     z = torch.empty(g.n, dtype=torch.float64, device="cuda")
     R2 = torch.empty(g.n, dtype=torch.uint64, device="cuda")
-    for u, c, Lx, mode in ((-1, C, L, 1), (g.n, C, L, 1), (0, 1.5, L, 1), (0, C, 0, 1), (0, C, L, 5)):
+    for c, mode in ((1.5, 1), (0.0, 1), (C, 5), (C, -1)):
         with pytest.raises(es.EsError) as e:
-            es.es_lde_plan(ctx, g, u, lv, Lx, Rk, c, mode, ell, z, R2)
+            es.es_lde_plan(ctx, g, Rk, c, mode, 3, ell, z, R2)
         assert e.value.status == es.ES_EINVAL
+    # an uncapped query whose rule asks for more than three exact levels
+    g2, og2 = pair(es, ctx, "chung_lu_2k")
+    s2 = torch.empty(g2.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(es.EsError) as e:
+        es.es_single_source(ctx, g2, 0, es.make_opts(C, 1e-4, 1, 1.0, lde=1, lde_max_level=0), s2)
+    assert e.value.status == es.ES_EUNSUPPORTED
+    # the context stays usable
+    es.es_single_source(ctx, g2, 0, es.make_opts(C, 1e-4, 1, 1e-4, lde=1), s2)
     # batches run Algorithm 2 only
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda")]
     with pytest.raises(es.EsError) as e:

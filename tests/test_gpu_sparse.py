@@ -169,7 +169,8 @@ def test_exact_diagonal_against_power_method(es, ctx):
 
 @pytest.mark.parametrize("mode", [1, 2])
 def test_with_local_exploitation(es, ctx, mode):
-    """Algorithm 3 reads levels 0..3 densely; the back-accumulation the sparse ones."""
+    """Algorithm 3 with sparse levels: the plan reads only the graph and R(k),
+    the back-accumulation the kept entries (one dense working slot)."""
     g, og = pair(es, ctx, "rmat_32k")
     u = int(np.argmax(og.din))
     eps, r_scale, seed, eps_s = 1e-4, 1e-3, 77, 1e-4
@@ -178,7 +179,7 @@ def test_with_local_exploitation(es, ctx, mode):
     L = ox.num_levels(C, eps)
     lv, pi = ox.forward_levels(og, u, C, L)
     Rk = ox.budget(pi, og.din, ox.total_samples(og.n, C, eps, r_scale), True)
-    ell, z, R2 = lde.plan(og, u, Rk, C, mode, source_max=min(3, L))
+    ell, z, R2 = lde.plan(og, Rk, C, mode)
     M = ox.walk_counts(og, R2, seed, C, nonstop=ell)
     D = lde.diag_estimate(R2, M, ell, z, C, og.din)
     kept = ox.sparsify_levels(lv, ox.sparse_threshold(C, eps_s))
@@ -187,7 +188,7 @@ def test_with_local_exploitation(es, ctx, mode):
     say(f"  mode {mode}: l(u)={st.lde_source_level} max|s - oracle| {err:.1e}")
     assert err <= S_TOL
     assert st.pairs == int(R2.sum())
-    assert st.level_bytes == 12 * int(np.count_nonzero(kept)) + 8 * (min(3, L) + 2) * g.n
+    assert st.level_bytes == 12 * int(np.count_nonzero(kept)) + 8 * g.n
 
 
 def test_tiny_graphs(es, ctx):
@@ -210,7 +211,7 @@ def test_tiny_graphs(es, ctx):
                         lv, pi = ox.forward_levels(og, u, C, L)
                         Rk = ox.budget(pi, og.din, ox.total_samples(n, C, eps, 1e-2), True)
                         if mode:
-                            ell, z, R2 = lde.plan(og, u, Rk, C, mode, source_max=min(3, L))
+                            ell, z, R2 = lde.plan(og, Rk, C, mode)
                             M = ox.walk_counts(og, R2, 3, C, nonstop=ell)
                             D = lde.diag_estimate(R2, M, ell, z, C, og.din)
                         else:
