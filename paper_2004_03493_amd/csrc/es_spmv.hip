@@ -8,7 +8,7 @@
 //
 // Both are bound by HBM/Infinity-Cache traffic: the CSR index stream is read once
 // per level and the gathered operand (8 bytes per entry) comes through the caches.
-// One workgroup of 256 lanes per row block: the block's column ids are streamed
+// One workgroup of kSpmvThreads (512) lanes per row block: the block's column ids are streamed
 // coalesced, the gathered operands staged in LDS, then each row is reduced by a
 // group of lanes sized to the block's average row length.
 #include <algorithm>
