@@ -257,6 +257,17 @@ es_status es_single_source(es_ctx* ctx, const es_graph* g, int32_t u, const es_q
 es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                   double* val_out);
 
+/* es_topk for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection and the same results, with its scratch (the selection state and
+ * 4096 candidate keys and ids) in a fixed 64 KiB array that each device holds
+ * for the life of the process, so the call allocates nothing.  Every call on
+ * one device shares that array (each call re-initialises it): calls that
+ * overlap in time on one device race, also across contexts.  Errors: as
+ * es_topk, and ES_EINVAL for k > 4096 (the array's capacity). */
+es_status es_topk_noalloc(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
+                          double* val_out);
+
 /* ---- local deterministic exploitation (Section 3.2, Algorithm 3) ----------
  * Z_l(k) is the probability that two sqrt(c)-walks from v_k first meet at
  * step l (Lemma 4 gives it from the transition probabilities), and

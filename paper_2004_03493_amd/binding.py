@@ -37,7 +37,7 @@ SYMBOLS = (
     "es_ctx_create", "es_ctx_destroy", "es_ctx_sync", "es_status_str", "es_last_error",
     "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_degrees",
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
-    "es_backward", "es_single_source", "es_topk", "es_batch", "es_batch_tuning",
+    "es_backward", "es_single_source", "es_topk", "es_topk_noalloc", "es_batch", "es_batch_tuning",
     "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
     "es_budget_weighted", "es_lde_plan", "es_walk_pairs_lde", "es_diag_lde",
     "es_forward_sparse", "es_sparse_capacity",
@@ -110,6 +110,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_backward": [P, P, P, i32, P, dbl, P],
         "es_single_source": [P, P, i32, ctypes.POINTER(QueryOpts), P, ctypes.POINTER(Stats)],
         "es_topk": [P, P, i32, i32, i32, P, P],
+        "es_topk_noalloc": [P, P, i32, i32, i32, P, P],
         "es_batch": [P, P, i32, P, P, i32, ctypes.POINTER(QueryOpts), ctypes.POINTER(BatchOpts), P,
                      ctypes.POINTER(Stats)],
         "es_batch_tuning": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
@@ -317,6 +318,12 @@ def es_topk(ctx: Context, s, n: int, exclude: int, k: int, idx_out, val_out=None
     _check(load_library().es_topk(ctx.handle, _ptr(s, torch.float64, n, "s"), n, exclude, k,
                                   _ptr(idx_out, torch.int32, k, "idx_out"),
                                   _ptr(val_out, torch.float64, k, "val_out")), ctx)
+
+
+def es_topk_noalloc(ctx: Context, s, n: int, exclude: int, k: int, idx_out, val_out=None):
+    _check(load_library().es_topk_noalloc(ctx.handle, _ptr(s, torch.float64, n, "s"), n, exclude, k,
+                                          _ptr(idx_out, torch.int32, k, "idx_out"),
+                                          _ptr(val_out, torch.float64, k, "val_out")), ctx)
 
 
 def es_batch(ctx: Context, graphs, graph_of_query, sources, opts: QueryOpts, outs, use_hip_graph: bool = False,

@@ -455,6 +455,10 @@ es_status es_ctx_create(int device, void* hip_stream, es_ctx** out) {
       return ES_EDEVICE;
     }
   }
+  if (es::topk_scratch_init(ctx) != ES_OK) {
+    es_ctx_destroy(ctx);
+    return ES_EDEVICE;
+  }
   *out = ctx;
   return ES_OK;
 }

@@ -267,6 +267,8 @@ es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, 
                           double c, double* s, double* s_tmp, const SparseLevels* sp = nullptr);
 es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
                       double* val_out);
+// Finds this context's device copy of the fixed top-k scratch (context creation).
+es_status topk_scratch_init(es_ctx* ctx);
 es_status build_plan(es_ctx* ctx, const int32_t* off_host, int32_t n, SpmvPlan* plan);
 void free_batch_plans(es_ctx* ctx);
 void free_plan(SpmvPlan* plan);

@@ -6,6 +6,8 @@
 // ids among the ties.  The k survivors are then sorted by (score desc, id asc)
 // with a bitonic sort in one workgroup's LDS.
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "es_internal.h"
 
@@ -14,6 +16,8 @@ namespace {
 
 constexpr int kTopkMax = 4096;
 constexpr int kHistThreads = 256;
+// fixed scratch of the allocation-free entry point (state, candidate keys and ids)
+constexpr size_t kTopkScratchBytes = 64 * 1024;
 
 struct TopkState {
   unsigned long long prefix;  // key bits fixed so far
@@ -178,14 +182,13 @@ __global__ __launch_bounds__(1024) void topk_sort_kernel(int32_t k, const double
   }
 }
 
-}  // namespace
+constexpr size_t kTopkBytes = ((sizeof(TopkState) + 15) & ~size_t(15)) +
+                               kTopkMax * (sizeof(unsigned long long) + sizeof(int32_t));
+static_assert(kTopkBytes <= kTopkScratchBytes, "top-k scratch too small");
 
-es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
-                      double* val_out) {
-  es_status stt;
-  const size_t bytes = sizeof(TopkState) + kTopkMax * (sizeof(unsigned long long) + sizeof(int32_t)) + 64;
-  char* ws = (char*)workspace(ctx, kWsTopk, bytes, &stt);
-  if (!ws) return stt;
+// The whole selection in a caller-given device buffer of kTopkBytes.
+es_status launch_topk_in(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
+                         double* val_out, char* ws) {
   auto* st = (TopkState*)ws;
   auto* ckey = (unsigned long long*)(ws + ((sizeof(TopkState) + 15) & ~size_t(15)));
   auto* cid = (int32_t*)(ckey + kTopkMax);
@@ -205,6 +208,39 @@ es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, 
   return ES_OK;
 }
 
+// Per device: the address of that device's copy of topk_scratch (found once,
+// at context creation).
+std::mutex scratch_mu;
+std::vector<void*> scratch_ptr;
+
+}  // namespace
+
+es_status launch_topk(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k, int32_t* idx_out,
+                      double* val_out) {
+  es_status stt;
+  char* ws = (char*)workspace(ctx, kWsTopk, kTopkBytes + 64, &stt);
+  if (!ws) return stt;
+  return launch_topk_in(ctx, s, n, exclude, k, idx_out, val_out, ws);
+}
+
+}  // namespace es
+
+// Scratch of es_topk_noalloc: one copy per device for the life of the process.
+static __device__ __align__(256) char topk_scratch[es::kTopkScratchBytes];
+
+namespace es {
+
+es_status topk_scratch_init(es_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if ((int)scratch_ptr.size() <= ctx->device) scratch_ptr.resize(ctx->device + 1, nullptr);
+  if (scratch_ptr[ctx->device]) return ES_OK;
+  void* p = nullptr;
+  // the device is current (es_ctx_create); the host name is not a device address
+  ES_CHECK_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(topk_scratch)));
+  scratch_ptr[ctx->device] = p;
+  return ES_OK;
+}
+
 }  // namespace es
 
 using namespace es;
@@ -217,4 +253,20 @@ extern "C" es_status es_topk(es_ctx* ctx, const double* s, int32_t n, int32_t ex
   if (k > kTopkMax) return fail(ctx, ES_EUNSUPPORTED, "k=%d above %d", k, kTopkMax);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   return launch_topk(ctx, s, n, exclude, k, idx_out, val_out);
+}
+
+extern "C" es_status es_topk_noalloc(es_ctx* ctx, const double* s, int32_t n, int32_t exclude, int32_t k,
+                                     int32_t* idx_out, double* val_out) {
+  if (!ctx || !s || !idx_out) return ES_EINVAL;
+  const int32_t avail = n - ((exclude >= 0 && exclude < n) ? 1 : 0);
+  if (n < 1 || k < 1 || k > avail) return fail(ctx, ES_EINVAL, "k=%d outside [1, %d]", k, avail);
+  if (k > kTopkMax) return fail(ctx, ES_EINVAL, "k=%d above the fixed scratch's %d", k, kTopkMax);
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (ctx->device < (int)scratch_ptr.size()) p = scratch_ptr[ctx->device];
+  }
+  if (!p) return fail(ctx, ES_EDEVICE, "top-k scratch of device %d not set up", ctx->device);
+  ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+  return launch_topk_in(ctx, s, n, exclude, k, idx_out, val_out, (char*)p);
 }
