@@ -5,7 +5,9 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "exactsim.h"
@@ -47,6 +49,18 @@ struct SpmvPlan {
 };
 
 struct BatchPlan;
+
+// Source-independent sums of a node's transition tables (Algorithm 3's level
+// rule and Lemma 4), cached per graph once computed: with S_j(v) the support
+// of (P^T)^j(v, .), N_j = sum of d_in over S_j, SN1_2 = sum over S_2 of
+// sum_{a in I(q)} d_in(a), C_j = sum_q (P^T)^j(v, q)^2, Cw_2 = sum_q
+// (P^T)^2(v, q)^2 / d_in(q).  Computed in exact integer arithmetic, so a
+// cached value equals a fresh one bit for bit.
+struct LdeNodeStats {
+  bool has2 = false, has3 = false;
+  uint64_t N2 = 0, SN1_2 = 0, N3 = 0;
+  double C2 = 0.0, Cw2 = 0.0, C3 = 0.0;
+};
 
 }  // namespace es
 
@@ -97,6 +111,8 @@ struct es_graph {
   // sum of d_in over I(v), and sum of 1/d_in over I(v)
   mutable long long* lde_n1 = nullptr;
   mutable double* lde_g = nullptr;
+  mutable std::unordered_map<int32_t, es::LdeNodeStats> lde_cache;
+  mutable std::mutex lde_mu;
 };
 
 struct es_ctx {

@@ -716,25 +716,51 @@ es_status launch_lde(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, double 
     ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   }
   auto din_of = [&](int32_t k) { return g->h_in_off[k + 1] - g->h_in_off[k]; };
-  // round 2: supports and tables of every listed node, two steps deep
-  std::vector<OriginLevel> r2;
-  ES_TRY(propagate(ctx, g, ids, std::vector<int32_t>(ncand, 2), r2));
+  // table sums of the listed nodes: from the graph's cache, else built now
+  // (depth 2) and cached
+  std::unique_lock<std::mutex> lock(g->lde_mu);
+  auto& cache = g->lde_cache;
+  auto fill = [&](const std::vector<int32_t>& nodes, const std::vector<int32_t>& dep) -> es_status {
+    if (nodes.empty()) return ES_OK;
+    std::vector<OriginLevel> r;
+    ES_TRY(propagate(ctx, g, nodes, dep, r));
+    for (size_t t = 0; t < nodes.size(); ++t) {
+      LdeNodeStats& e = cache[nodes[t]];
+      const OriginLevel& s2 = r[t * (kMaxLevel + 1) + 2];
+      e.has2 = true;
+      e.N2 = s2.N;
+      e.SN1_2 = s2.SN1;
+      e.C2 = s2.C;
+      e.Cw2 = s2.Cw;
+      if (dep[t] >= 3) {
+        const OriginLevel& s3 = r[t * (kMaxLevel + 1) + 3];
+        e.has3 = true;
+        e.N3 = s3.N;
+        e.C3 = s3.C;
+      }
+    }
+    return ES_OK;
+  };
+  {
+    std::vector<int32_t> need;
+    for (int32_t k : ids)
+      if (!cache[k].has2) need.push_back(k);
+    ES_TRY(fill(need, std::vector<int32_t>(need.size(), 2)));
+  }
+  // round 2
   std::vector<int32_t> lv(ncand, 2);
   std::vector<double> z(ncand, 0.0);
   std::vector<long long> E2(ncand);
   std::vector<int32_t> deep;  // indices of nodes that take (at least) round 3
   for (int32_t i = 0; i < ncand; ++i) {
-    const OriginLevel& s2 = r2[(size_t)i * (kMaxLevel + 1) + 2];
+    const LdeNodeStats& e = cache[ids[i]];
     const double T = (2.0 * (double)R[i]) / sc;
-    const long long cost2 = 2 * (long long)s2.N + sN1[i];
+    const long long cost2 = 2 * (long long)e.N2 + sN1[i];
     E2[i] = E1[i] + cost2;
     if ((double)E2[i] >= T || cost2 == 0 || cap == 2) lv[i] = 2;
     else deep.push_back(i);
   }
   // round 3: three-step tables of the deep nodes, two-step tables of their in-neighbours
-  std::vector<std::vector<int32_t>> nbrs(deep.size());
-  std::vector<OriginLevel> r3;
-  std::vector<int32_t> o3, d3;
   if (!deep.empty()) {
     // in-neighbour rows of the deep nodes, packed on the device
     const int32_t nd = (int32_t)deep.size();
@@ -757,35 +783,37 @@ es_status launch_lde(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, double 
     std::vector<int32_t> flat((size_t)dst[nd]);
     ES_CHECK_HIP(ctx, hipMemcpyAsync(flat.data(), packed, 4 * flat.size(), hipMemcpyDeviceToHost, ctx->stream));
     ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> need, dep;
+    for (int32_t t = 0; t < nd; ++t)
+      if (!cache[rows[t]].has3) {
+        need.push_back(rows[t]);
+        dep.push_back(3);
+      }
+    std::vector<int32_t> nb(flat);
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    for (int32_t a : nb) {
+      const LdeNodeStats& e = cache[a];
+      if (!e.has2 && std::find(need.begin(), need.end(), a) == need.end()) {
+        need.push_back(a);
+        dep.push_back(2);
+      }
+    }
+    ES_TRY(fill(need, dep));
     for (int32_t t = 0; t < nd; ++t) {
-      nbrs[t].assign(flat.begin() + dst[t], flat.begin() + dst[t + 1]);
-      o3.push_back(rows[t]);
-      d3.push_back(3);
-    }
-    // in-neighbours as origins of depth 2 (each node once)
-    std::vector<int32_t> all;
-    for (auto& v : nbrs) all.insert(all.end(), v.begin(), v.end());
-    std::sort(all.begin(), all.end());
-    all.erase(std::unique(all.begin(), all.end()), all.end());
-    for (int32_t a : all) {
-      o3.push_back(a);
-      d3.push_back(2);
-    }
-    ES_TRY(propagate(ctx, g, o3, d3, r3));
-    auto lookup = [&](int32_t a) -> const OriginLevel& {
-      const size_t pos = deep.size() + (size_t)(std::lower_bound(all.begin(), all.end(), a) - all.begin());
-      return r3[pos * (kMaxLevel + 1) + 2];
-    };
-    for (size_t t = 0; t < deep.size(); ++t) {
       const int32_t i = deep[t];
+      const LdeNodeStats& e = cache[rows[t]];
+      double sc2 = 0.0;
+      long long sN2 = 0;
+      for (long long p = dst[t]; p < dst[t + 1]; ++p) {
+        const LdeNodeStats& a = cache[flat[p]];
+        sc2 += a.C2;
+        sN2 += (long long)a.N2;
+      }
       lv[i] = 3;
       if (!capped) {
         // the printed rule asks for Z_4 unless round 3 reaches the budget or runs dry
-        const OriginLevel& s2 = r2[(size_t)i * (kMaxLevel + 1) + 2];
-        const OriginLevel& s3 = r3[t * (kMaxLevel + 1) + 3];
-        long long sN2 = 0;
-        for (int32_t a : nbrs[t]) sN2 += (long long)lookup(a).N;
-        const long long cost3 = 2 * (long long)s3.N + sN2 + (long long)s2.SN1;
+        const long long cost3 = 2 * (long long)e.N3 + sN2 + (long long)e.SN1_2;
         const double T = (2.0 * (double)R[i]) / sc;
         if (!((double)(E2[i] + cost3) >= T || cost3 == 0))
           return fail(ctx, ES_EUNSUPPORTED,
@@ -793,28 +821,21 @@ es_status launch_lde(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, double 
                       "round 3, budget %.6g); cap the level with lde_max_level",
                       kMaxLevel, (unsigned long long)R[i], E2[i] + cost3, T);
       }
-    }
-    // Z_3 terms
-    for (size_t t = 0; t < deep.size(); ++t) {
-      const int32_t i = deep[t];
-      double sc2 = 0.0;
-      for (int32_t a : nbrs[t]) sc2 += lookup(a).C;
-      const OriginLevel& s2 = r2[(size_t)i * (kMaxLevel + 1) + 2];
-      const OriginLevel& s3 = r3[t * (kMaxLevel + 1) + 3];
-      const double iu = 1.0 / (double)din_of(ids[i]);
+      const double iu = 1.0 / (double)din_of(rows[t]);
       const double iu2 = iu * iu;
-      z[i] = cl3 * (((s3.C - s2.Cw) + iu2 * A2[i]) - iu2 * sc2);
+      z[i] = cl3 * (((e.C3 - e.Cw2) + iu2 * A2[i]) - iu2 * sc2);
     }
   }
   // Z_1 + Z_2 (+ Z_3) of every listed node
   for (int32_t i = 0; i < ncand; ++i) {
-    const OriginLevel& s2 = r2[(size_t)i * (kMaxLevel + 1) + 2];
+    const LdeNodeStats& e = cache[ids[i]];
     const double d = (double)din_of(ids[i]);
     const double iu = 1.0 / d;
     const double z1 = c / d;
-    const double z2 = cl2 * (s2.C - (iu * iu) * Gk[i]);
+    const double z2 = cl2 * (e.C2 - (iu * iu) * Gk[i]);
     z[i] = (z1 + z2) + z[i];
   }
+  lock.unlock();
   auto* up = (int32_t*)workspace(ctx, kWsLdeSums, 16 * (size_t)ncand, &st);
   if (!up) return st;
   auto* zs = (double*)((char*)up + 8 * (size_t)ncand);

@@ -151,6 +151,29 @@ def test_plan_uncapped(es, ctx):
         g2.close()
 
 
+def test_plan_cache_gives_the_same_bits(es, ctx):
+    """The per-graph cache of table sums: a plan on a graph that has answered
+    other queries equals, bit for bit, the plan on a fresh handle of the same
+    edges, for every source order."""
+    n, s_, d_ = GRAPHS["hubs"]()
+    og = OracleGraph(n, s_, d_)
+    us = [int(x) for x in np.argsort(-og.din)[:3]] + [7]
+    ga = es.Graph(ctx, n, s_, d_)
+    plans = {}
+    for u in us:  # warm: each plan after the previous ones filled the cache
+        L, lv, Rk, _, _ = stages(es, ctx, ga, og, u, 1e-4, 1e-1)
+        plans[u] = [host(t).copy() for t in gpu_plan(es, ctx, ga, Rk, lde.MODE_REDUCED)]
+    ga.close()
+    for u in reversed(us):  # cold: a new handle per source
+        gb = es.Graph(ctx, n, s_, d_)
+        L, lv, Rk, _, _ = stages(es, ctx, gb, og, u, 1e-4, 1e-1)
+        cold = [host(t) for t in gpu_plan(es, ctx, gb, Rk, lde.MODE_REDUCED)]
+        for a, b in zip(plans[u], cold):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), u
+        say(f"  u={u}: {int((cold[0] >= 2).sum())} nodes with l >= 2, warm = cold")
+        gb.close()
+
+
 @pytest.mark.parametrize("name", ["chung_lu_2k", "rmat_32k", "hubs"])
 def test_nonstop_walks_bitwise(es, ctx, name):
     g, og = pair(es, ctx, name)
