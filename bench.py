@@ -249,7 +249,11 @@ def batch_block(args, which, r_scale, steps, warmup, hip_graph, warm_r_scale=Non
             f"GB (dense {bstats[-1].level_bytes / 1e9:.3f} GB)")
         sp_out = {"sparse_eps": eps, "queries_per_s": len(sources) / t_sparse,
                   "level_entries": int(sp_stats[-1].level_entries), "level_bytes": int(sp_stats[-1].level_bytes)}
-    tuned = sorted({(g.n, es.es_batch_tuning(g, min(64, goq.count(gi)))) for gi, g in enumerate(graphs)})
+    # per graph: (n, source-block width chosen, (lane-group width, entries per lane) of that block)
+    tuned = []
+    for gi, g in enumerate(graphs):
+        bw = es.es_batch_block_width(g, goq.count(gi)) or min(64, goq.count(gi))
+        tuned.append((g.n, bw, es.es_batch_tuning(g, bw)))
     nq = len(sources)
     for g in graphs:
         g.close()
@@ -269,7 +273,7 @@ def batch_block(args, which, r_scale, steps, warmup, hip_graph, warm_r_scale=Non
         "pairs_requested": int(bstats[-1].pairs_requested),
         "single_source_pairs": int(pairs_single),
         "single_source_ms": {"forward": fwd_ms, "walk": walk_ms, "backward": back_ms, "total": t_single * 1e3},
-        "tuned_width_rows": tuned,
+        "tuned_block_width_lanes_rows": tuned,
         "dense_level_bytes": int(bstats[-1].level_bytes),
         "sparse": sp_out,
     }

@@ -371,11 +371,15 @@ typedef struct {
                              tilings of the level SpMM and keep the fastest                        */
   int32_t force_width;    /* 0, or lanes per row of the level SpMM (8, 16, 32 or 64, >= block width) */
   int32_t force_rows;     /* 0, or entries per lane per tile (rows per wave pass)                   */
+  int32_t block_width;    /* 0: sources per block chosen by the autotuner when it is on (the width
+                             of 64, 32, 16 or 8 whose level SpMM costs least per source), else 64;
+                             1..64: that many sources per block                                    */
 } es_batch_opts;
 
 /* Many single-source queries at once (same c, eps, seed, r_scale, alloc):
  * query q asks for s(sources[q], .) on graphs[graph_of_query[q]].  Queries of
- * one graph are grouped in source blocks of at most 64; each block runs the
+ * one graph are grouped in source blocks of at most 64 (es_batch_opts
+ * block_width); each block runs the
  * level SpMV as one SpMM over its sources (Algorithm 1's l-hop PPR and
  * back-accumulation for every source at once) in a single fused launch per level across all blocks
  * and graphs, and the blocks draw shared walk samples: node k of a block
@@ -391,8 +395,8 @@ typedef struct {
  * stats (nullable): pairs = pairs simulated, pairs_requested = sum over queries,
  * meets = sum over queries of sum_k M(k), level_entries / level_bytes over the
  * batch; times are 0 except ms_walk (all walks).
- * Errors: as es_single_source; ES_EINVAL for a bad graph index, source or
- * width; ES_EUNSUPPORTED for d_override, the learned allocation, Algorithm 3
+ * Errors: as es_single_source; ES_EINVAL for a bad graph index, source,
+ * width or block width; ES_EUNSUPPORTED for d_override, the learned allocation, Algorithm 3
  * (lde != 0), or sparse levels when a batch holds 2^31 or more
  * (node, source) entries. */
 es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, const int32_t* graph_of_query,
@@ -402,6 +406,9 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
 /* The tiling the autotuner chose for graph g and source-block width B
  * (host outputs; 0 if not tuned yet). */
 es_status es_batch_tuning(const es_graph* g, int32_t B, int32_t* width, int32_t* rows);
+/* The source-block width the autotuner chose for a batch of S queries on g
+ * (host output; 0 if not tuned yet). */
+es_status es_batch_block_width(const es_graph* g, int32_t S, int32_t* width);
 
 #ifdef __cplusplus
 }

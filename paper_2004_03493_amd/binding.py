@@ -37,7 +37,7 @@ SYMBOLS = (
     "es_ctx_create", "es_ctx_destroy", "es_ctx_sync", "es_status_str", "es_last_error",
     "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_degrees",
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
-    "es_backward", "es_single_source", "es_topk", "es_topk_noalloc", "es_batch", "es_batch_tuning",
+    "es_backward", "es_single_source", "es_topk", "es_topk_noalloc", "es_batch", "es_batch_tuning", "es_batch_block_width",
     "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
     "es_budget_weighted", "es_lde_plan", "es_walk_pairs_lde", "es_diag_lde",
     "es_forward_sparse", "es_sparse_capacity",
@@ -59,7 +59,8 @@ class QueryOpts(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("use_hip_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("force_width", ctypes.c_int32), ("force_rows", ctypes.c_int32)]
+                ("force_width", ctypes.c_int32), ("force_rows", ctypes.c_int32),
+                ("block_width", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -114,6 +115,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_batch": [P, P, i32, P, P, i32, ctypes.POINTER(QueryOpts), ctypes.POINTER(BatchOpts), P,
                      ctypes.POINTER(Stats)],
         "es_batch_tuning": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "es_batch_block_width": [P, i32, ctypes.POINTER(i32)],
         "es_mlp_num_params": [],
         "es_mlp_features": [P, P, dbl, P],
         "es_mlp_infer": [P, P, P, i64, dbl, P, P],
@@ -327,7 +329,8 @@ def es_topk_noalloc(ctx: Context, s, n: int, exclude: int, k: int, idx_out, val_
 
 
 def es_batch(ctx: Context, graphs, graph_of_query, sources, opts: QueryOpts, outs, use_hip_graph: bool = False,
-             autotune: bool = True, force_width: int = 0, force_rows: int = 0, want_stats: bool = True):
+             autotune: bool = True, force_width: int = 0, force_rows: int = 0, want_stats: bool = True,
+             block_width: int = 0):
     """Batched queries: graphs is a list of Graph, outs a list of float64 device tensors."""
     import numpy as np
     lib = load_library()
@@ -343,7 +346,7 @@ def es_batch(ctx: Context, graphs, graph_of_query, sources, opts: QueryOpts, out
         n = graphs[gi].n if 0 <= gi < len(graphs) else None  # a bad index is the library's to report
         ptrs.append(_ptr(outs[q], torch.float64, n, f"outs[{q}]").value)
     op = (ctypes.c_void_p * nq)(*ptrs)
-    bo = BatchOpts(int(use_hip_graph), int(autotune), int(force_width), int(force_rows))
+    bo = BatchOpts(int(use_hip_graph), int(autotune), int(force_width), int(force_rows), int(block_width))
     st = Stats()
     _check(lib.es_batch(ctx.handle, gh, len(graphs), goq.ctypes.data, src.ctypes.data, nq, ctypes.byref(opts),
                         ctypes.byref(bo), op, ctypes.byref(st) if want_stats else None), ctx)
@@ -355,6 +358,12 @@ def es_batch_tuning(g: Graph, B: int):
     r = ctypes.c_int32()
     _check(load_library().es_batch_tuning(g.handle, B, ctypes.byref(w), ctypes.byref(r)))
     return w.value, r.value
+
+
+def es_batch_block_width(g: Graph, S: int) -> int:
+    w = ctypes.c_int32()
+    _check(load_library().es_batch_block_width(g.handle, S, ctypes.byref(w)))
+    return w.value
 
 
 def es_mlp_num_params() -> int:

@@ -471,11 +471,12 @@ int32_t pow2_at_least(int32_t x) {
   return p;
 }
 
-bool find_tuned(const es_graph* g, int32_t B, int32_t* W, int32_t* G) {
+bool find_tuned(const es_graph* g, int32_t B, int32_t* W, int32_t* G, float* ms = nullptr) {
   for (auto& t : g->tuned)
-    if (t.first == B) {
-      *W = t.second.first;
-      *G = t.second.second;
+    if (t.B == B) {
+      *W = t.W;
+      *G = t.G;
+      if (ms) *ms = t.ms;
       return true;
     }
   return false;
@@ -703,7 +704,7 @@ es_status build_batch_plan(es_ctx* ctx, BatchPlan& p, const std::vector<BatchBlo
 
 // Time the forward SpMM of one block for each candidate tiling; keep the fastest.
 es_status autotune(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opts* o, int32_t* bestW,
-                   int32_t* bestG) {
+                   int32_t* bestG, float* best_ms) {
   std::vector<int32_t> widths;
   for (int32_t w = pow2_at_least(std::max(B, 1)); w <= 64; w <<= 1) widths.push_back(std::max(w, 8));
   widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
@@ -772,6 +773,45 @@ es_status autotune(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opt
     }
   }
   ES_CHECK_HIP(ctx, hipGetLastError());
+  *best_ms = best;
+  return ES_OK;
+}
+
+// The tiling of a block of width B on g: tuned once and kept in the graph.
+es_status tiling_for(es_ctx* ctx, const es_graph* g, int32_t B, const es_query_opts* o, int32_t* W, int32_t* G,
+                     float* ms) {
+  if (find_tuned(g, B, W, G, ms)) return ES_OK;
+  ES_TRY(autotune(ctx, g, B, o, W, G, ms));
+  const_cast<es_graph*>(g)->tuned.push_back({B, *W, *G, *ms});
+  return ES_OK;
+}
+
+// Source-block width for S queries on g: the width (64, 32, 16 or 8, not
+// above what S fills) whose tuned level SpMM costs least per source.
+es_status block_width_for(es_ctx* ctx, const es_graph* g, int32_t S, const es_query_opts* o, int32_t* width) {
+  for (auto& t : g->tuned_block)
+    if (t.first == S) {
+      *width = t.second;
+      return ES_OK;
+    }
+  int32_t best_w = std::min(S, kBatchMaxB);
+  if (S > 8 && g->n >= kBatchMaxB) {
+    float best = 1e30f;
+    for (int32_t w = kBatchMaxB; w >= 8; w >>= 1) {
+      if (w > pow2_at_least(S)) continue;
+      const int32_t bw = std::min(w, S);
+      int32_t W, G;
+      float ms;
+      ES_TRY(tiling_for(ctx, g, bw, o, &W, &G, &ms));
+      const float per_source = ms / (float)bw;
+      if (per_source < best) {
+        best = per_source;
+        best_w = bw;
+      }
+    }
+  }
+  const_cast<es_graph*>(g)->tuned_block.push_back({S, best_w});
+  *width = best_w;
   return ES_OK;
 }
 
@@ -791,6 +831,14 @@ es_status es_batch_tuning(const es_graph* g, int32_t B, int32_t* width, int32_t*
   return ES_OK;
 }
 
+es_status es_batch_block_width(const es_graph* g, int32_t S, int32_t* width) {
+  if (!g || !width) return ES_EINVAL;
+  *width = 0;
+  for (auto& t : g->tuned_block)
+    if (t.first == S) *width = t.second;
+  return ES_OK;
+}
+
 es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, const int32_t* graph_of_query,
                    const int32_t* sources, int32_t nq, const es_query_opts* o, const es_batch_opts* bo,
                    double* const* s_out, es_stats* stats) {
@@ -804,8 +852,10 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   if (o->lde != 0) return fail(ctx, ES_EUNSUPPORTED, "batches run Algorithm 2 only (lde = 0)");
   if (!(o->sparse_eps >= 0.0 && o->sparse_eps < 1.0))
     return fail(ctx, ES_EINVAL, "sparse_eps=%g outside [0, 1)", o->sparse_eps);
-  es_batch_opts defaults{0, 1, 0, 0};
+  es_batch_opts defaults{0, 1, 0, 0, 0};
   const es_batch_opts& b = bo ? *bo : defaults;
+  if (b.block_width < 0 || b.block_width > kBatchMaxB)
+    return fail(ctx, ES_EINVAL, "block_width=%d outside 0..%d", b.block_width, kBatchMaxB);
   if (b.force_width && (b.force_width < 8 || b.force_width > 64 || (b.force_width & (b.force_width - 1))))
     return fail(ctx, ES_EINVAL, "force_width=%d", b.force_width);
   if (b.force_rows < 0) return fail(ctx, ES_EINVAL, "force_rows=%d", b.force_rows);
@@ -822,16 +872,22 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
     const double R = total_samples(graphs[gi]->n, o->c, o->eps, o->r_scale);
     if (R + (double)graphs[gi]->n >= 9.2e18) return fail(ctx, ES_EOVERFLOW, "R=%g: sample count may reach 2^63", R);
   }
-  // blocks of at most 64 queries per graph, in graph order
+  // blocks per graph, in graph order: of the forced width, of the width the
+  // tuner finds cheapest per source, or of 64
   std::vector<BatchBlock> blocks;
   for (int32_t gi = 0; gi < ngraphs; ++gi) {
     std::vector<int32_t> qs;
     for (int32_t q = 0; q < nq; ++q)
       if (graph_of_query[q] == gi) qs.push_back(q);
-    for (size_t s0 = 0; s0 < qs.size(); s0 += kBatchMaxB) {
+    if (qs.empty()) continue;
+    int32_t bw = kBatchMaxB;
+    if (b.block_width) bw = b.block_width;
+    else if (b.autotune && !b.force_width && !b.force_rows)
+      ES_TRY(block_width_for(ctx, graphs[gi], (int32_t)qs.size(), o, &bw));
+    for (size_t s0 = 0; s0 < qs.size(); s0 += (size_t)bw) {
       BatchBlock bl;
       bl.g = graphs[gi];
-      bl.queries.assign(qs.begin() + s0, qs.begin() + std::min(qs.size(), s0 + kBatchMaxB));
+      bl.queries.assign(qs.begin() + s0, qs.begin() + std::min(qs.size(), s0 + (size_t)bw));
       bl.B = (int32_t)bl.queries.size();
       blocks.push_back(bl);
     }
@@ -845,8 +901,8 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
       if (W < bl.B) return fail(ctx, ES_EINVAL, "force_width=%d below block width %d", W, bl.B);
     } else if (!find_tuned(bl.g, bl.B, &W, &G)) {
       if (b.autotune) {
-        ES_TRY(autotune(ctx, bl.g, bl.B, o, &W, &G));
-        const_cast<es_graph*>(bl.g)->tuned.push_back({bl.B, {W, G}});
+        float ms;
+        ES_TRY(tiling_for(ctx, bl.g, bl.B, o, &W, &G, &ms));
       } else {
         W = std::max(8, pow2_at_least(bl.B));
         G = 32;

@@ -97,8 +97,15 @@ struct es_graph {
   int32_t* int_of = nullptr;   // [n]    external id -> internal id
   std::vector<int32_t> h_int_of;
   std::vector<int32_t> h_out_off, h_in_off;  // host copies of the offsets (batch tiling)
-  // autotuned batch tiling per source-block width B: (lanes per row, entries per lane)
-  std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> tuned;
+  // autotuned batch tiling per source-block width B: lanes per row W, entries
+  // per lane G and the forward SpMM's time for three levels (ms)
+  struct Tuned {
+    int32_t B, W, G;
+    float ms;
+  };
+  std::vector<Tuned> tuned;
+  // block width the tuner chose for a graph's batch of S queries, by S
+  std::vector<std::pair<int32_t, int32_t>> tuned_block;
   es::SpmvPlan fwd;            // over the out-CSR
   es::SpmvPlan back;           // over the in-CSR
   // learned allocation: predicted variances v(k) by internal id for the

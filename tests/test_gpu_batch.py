@@ -283,8 +283,33 @@ def test_batch_autotune_records_choice(es, ctx, graphs):
     srcs = pick(og, 20, 4)
     opts = es.make_opts(C, 1e-4, 9, 1e-3)
     run_batch(es, ctx, [g], [0] * 20, srcs, opts, autotune=True)
-    w, rows = es.es_batch_tuning(g, 20)
-    assert w in (32, 64) and rows > 0
+    bw = es.es_batch_block_width(g, 20)
+    assert bw in (8, 16, 20)
+    w, rows = es.es_batch_tuning(g, bw)
+    assert w >= bw and w in (8, 16, 32, 64) and rows > 0
+    say(f"  20 sources: blocks of {bw}, lane groups of {w}, {rows} entries per lane")
+
+
+@pytest.mark.parametrize("which", [1, 0])
+def test_batch_block_widths_agree(es, ctx, graphs, which):
+    """Any source-block width gives every source its single-source answer
+    (the same walk and meeting counts; s within float64 summation)."""
+    g, og = graphs[which]
+    srcs = pick(og, 37, 8)
+    opts = es.make_opts(C, 1e-4, 29, 1e-3)
+    ref, st0 = run_batch(es, ctx, [g], [0] * 37, srcs, opts, autotune=False)
+    for bw in (1, 8, 16, 32, 64):
+        outs, st = run_batch(es, ctx, [g], [0] * 37, srcs, opts, autotune=False, block_width=bw)
+        assert st.meets == st0.meets and st.pairs_requested == st0.pairs_requested
+        for a, b in zip(ref, outs):
+            assert np.abs(a - b).max() <= 1e-13, bw
+    outs, st = run_batch(es, ctx, [g], [0] * 37, srcs, opts, autotune=True)
+    say(f"  graph {which}: autotuned block width {es.es_batch_block_width(g, 37)}")
+    for a, b in zip(ref, outs):
+        assert np.abs(a - b).max() <= 1e-13
+    u, s_ = srcs[5], outs[5]
+    single_s, _ = single(es, ctx, g, u, opts)
+    assert np.abs(s_ - single_s).max() <= 1e-13
 
 
 def test_batch_argument_errors(es, ctx, graphs):
@@ -297,6 +322,8 @@ def test_batch_argument_errors(es, ctx, graphs):
         es.es_batch(ctx, [g], [0], [g.n], opts, out)
     with pytest.raises(es.EsError):
         es.es_batch(ctx, [g], [0], [0], opts, out, force_width=12)
+    with pytest.raises(es.EsError):
+        es.es_batch(ctx, [g], [0], [0], opts, out, block_width=65)
     bad = es.make_opts(C, 1e-4, 1, 1e-3, sparse_eps=1.5)
     with pytest.raises(es.EsError):
         es.es_batch(ctx, [g], [0], [0], bad, out)
