@@ -27,7 +27,6 @@ namespace {
 
 constexpr int kBatchMaxB = 64;
 constexpr int kSpmmThreads = 256;  // four independent waves
-constexpr int kLongRow = 1024;
 constexpr double kFix = 0x1p62;
 constexpr double kFixInv = 0x1p-62;
 
@@ -50,22 +49,6 @@ struct BEntry {
   int64_t node_base;  // first flat node of the block (arrays of length n)
   int64_t long_base;  // first long-row slot (x B) of the block
   int64_t src_base;   // first source / output index of the block
-};
-
-struct MTile {
-  int32_t entry;
-  int32_t row0;
-  int32_t row1;  // < 0: chunk of long row slot (-row1 - 1)
-  int32_t e0;
-  int32_t e1;
-  int32_t row;   // long chunk: the row
-};
-
-struct LongRow {
-  int32_t entry;
-  int32_t row;
-  int32_t slot;  // first partial slot; the row's chunks use slot .. slot + nch - 1
-  int32_t nch;
 };
 
 // ---- level operators ------------------------------------------------------
@@ -433,37 +416,6 @@ void free_batch_plans(es_ctx* ctx) {
 }
 
 namespace {
-
-// Tiles over the rows of one block for one CSR direction.
-void make_tiles(const std::vector<int32_t>& off, int32_t n, int32_t entry, int32_t W, int32_t G,
-                std::vector<MTile>& tiles, std::vector<LongRow>& longs, int32_t& nlong) {
-  const int32_t P = 64 / W;
-  const int64_t target = (int64_t)P * G;
-  int32_t r = 0;
-  while (r < n) {
-    const int32_t deg = off[r + 1] - off[r];
-    if (deg > kLongRow) {
-      // one partial slot per chunk
-      const int32_t first = nlong;
-      for (int32_t e0 = off[r]; e0 < off[r + 1]; e0 += kLongRow)
-        tiles.push_back(MTile{entry, r, -(nlong++ + 1), e0, std::min(e0 + kLongRow, off[r + 1]), r});
-      longs.push_back(LongRow{entry, r, first, nlong - first});
-      ++r;
-      continue;
-    }
-    const int32_t r0 = r;
-    int64_t acc = 0;
-    while (r < n) {
-      const int32_t d = off[r + 1] - off[r];
-      if (d > kLongRow) break;
-      const int64_t w = std::max<int32_t>(d, 1);
-      if (r > r0 && acc + w > target) break;
-      acc += w;
-      ++r;
-    }
-    tiles.push_back(MTile{entry, r0, r, 0, 0, 0});
-  }
-}
 
 int32_t pow2_at_least(int32_t x) {
   int32_t p = 1;

@@ -10,6 +10,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "es_host.h"
 #include "exactsim.h"
 
 namespace es {
@@ -25,16 +26,7 @@ namespace es {
 //    sums are combined in chunk order by the last chunk to finish.
 // ---------------------------------------------------------------------------
 constexpr int kSpmvThreads = 512;
-constexpr int kSpmvNnz = 8192;
-constexpr int kSpmvRows = 512;
-constexpr int kLongChunk = 8192;
-
-struct BlockDesc {
-  int32_t row0;  // first row
-  int32_t row1;  // one past the last row; < 0: long-row chunk of long row (-row1 - 1)
-  int32_t e0;    // first entry
-  int32_t e1;    // one past the last entry
-};
+// kSpmvNnz, kSpmvRows, kLongChunk and BlockDesc: es_host.h
 
 struct SpmvPlan {
   BlockDesc* blocks = nullptr;  // device
