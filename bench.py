@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--cpu-sample-pairs", type=float, default=2e8)
     p.add_argument("--copy-calibration", action="store_true",
                    help="after the timed region, copy 1 GiB once (reference dispatch for HBM counters)")
-    p.add_argument("--workload", default="single", choices=["single", "batch64", "uneven", "rmat42m", "cl2k"],
+    p.add_argument("--workload", default="single", choices=["single", "batch64", "uneven", "rmat42m", "cl2k", "equal_error"],
                    help="single: the R-MAT 2^20 single-source line; batch64 / uneven: batched queries "
                         "against single-source queries on the same GPU; rmat42m: R-MAT n=4.2e7, m=1.4e9 "
                         "with the learned walk budget against the pi^2 rule")
@@ -439,6 +439,114 @@ def learned_main(args):
     print(json.dumps(out), flush=True)
 
 
+def equal_error_main(args):
+    """R-MAT n=4.2e7, m=1.4e9: the walk pairs the pi^2 rule needs to reach the
+    learned allocation's MaxError.  MaxError against a pi^2 run with
+    --ref-factor times the budget (another walk seed), mean over four sources
+    and two seeds; the pi^2 rule at 1x..4x the budget traces MaxError against
+    pairs and a log-log interpolation between the two budgets that bracket
+    the learned error gives the equal-error pairs.  Two networks: trained on
+    the method's own D estimates (Algorithm 2 with a uniform 4000 pairs per
+    node) on the configured smaller workloads (Chung-Lu 2,000, R-MAT 2^20,
+    R-MAT 4.8e6), and on three other graphs of the same families."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2004_03493_amd import binding as es
+    from paper_2004_03493_amd import learned
+
+    wl = workloads.RMAT_42M
+    c, eps = wl.c, wl.eps
+    ctx = es.Context(0)
+    train_sets = {
+        "configured_workloads": [("chung_lu", workloads.CHUNG_LU_2K.n, workloads.CHUNG_LU_2K.m,
+                                  workloads.CHUNG_LU_2K.seed_graph),
+                                 ("rmat", workloads.RMAT_1M.n, workloads.RMAT_1M.m, workloads.RMAT_1M.seed_graph),
+                                 ("rmat", workloads.RMAT_4M8.n, workloads.RMAT_4M8.m, workloads.RMAT_4M8.seed_graph)],
+        "other_graphs": [("rmat", 1 << 16, 33 << 16, 601), ("rmat", 1 << 18, 33 << 18, 602),
+                         ("chung_lu", 1 << 16, 20 << 16, 603)],
+    }
+    nets = {}
+    for name, specs in train_sets.items():
+        t0 = time.time()
+        Fs, Rs, Ms = [], [], []
+        for kind, n, m, seed in specs:
+            s_, d_ = workloads.rmat(n, m, seed) if kind == "rmat" else workloads.chung_lu(n, m, seed)
+            gt = es.Graph(ctx, n, s_, d_)
+            F, R, M = learned.collect(ctx, gt, c, 4000, seed + 2)
+            Fs.append(F); Rs.append(R); Ms.append(M)
+            torch.cuda.synchronize()
+            gt.close()
+        F, R, M = torch.cat(Fs), torch.cat(Rs), torch.cat(Ms)
+        w, losses = learned.train(ctx, F, R, M, c, epochs=600, lr=3e-3, seed=7)
+        nets[name] = (w, int(F.shape[0]), float(losses[0]), float(losses[-1]))
+        del F, R, M, Fs, Rs, Ms
+        log(f"# network '{name}' trained on {nets[name][1]} nodes in {time.time() - t0:.1f}s, "
+            f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    src, dst = wl.graph()
+    sources = [int(x) for x in wl.sources(dst)][:4]
+    g = es.Graph(ctx, wl.n, src, dst)
+    del src, dst
+    log(f"# graph on device: n={g.n} m={g.m}")
+    s = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    refs = {}
+    for u in sources:
+        es.es_single_source(ctx, g, u, es.make_opts(c, eps, wl.seed_walk + 1000, args.r_scale * args.ref_factor), s)
+        refs[u] = s.clone()
+        log(f"# reference u={u} done")
+    seeds = (wl.seed_walk + 1, wl.seed_walk + 2)
+
+    def run(alloc, r_scale):
+        errs, pairs = [], 0
+        for u in sources:
+            for seed in seeds:
+                st = es.es_single_source(ctx, g, u, es.make_opts(c, eps, seed, r_scale, alloc=alloc), s)
+                errs.append(float((s - refs[u]).abs().max()))
+                pairs += st.pairs
+        return float(np.mean(errs)), pairs, errs
+
+    curve = []
+    for f in (1.0, 1.5, 2.0, 3.0, 4.0):
+        e, p, _ = run(es.ES_ALLOC_PI2, args.r_scale * f)
+        curve.append((f, e, p))
+        log(f"# pi2 x{f:g}: {p:.3g} pairs, MaxError {e:.3e}")
+    errs = np.array([e for _, e, _ in curve])
+    pairs = np.array([p for _, _, p in curve], dtype=np.float64)
+    out_nets = {}
+    for name, (w, nrows, l0, l1) in nets.items():
+        es.es_mlp_load(ctx, w)
+        e_l, p_l, per_query = run(es.ES_ALLOC_LEARNED, args.r_scale)
+        p_eq = None
+        if errs[-1] < e_l < errs[0]:
+            k = int(np.searchsorted(-errs, -e_l))
+            x0, x1 = np.log(pairs[k - 1]), np.log(pairs[k])
+            y0, y1 = np.log(errs[k - 1]), np.log(errs[k])
+            p_eq = float(np.exp(x0 + (np.log(e_l) - y0) * (x1 - x0) / (y1 - y0)))
+        out_nets[name] = {
+            "training_rows": nrows, "loss_first": l0, "loss_last": l1,
+            "learned_pairs": p_l, "learned_max_error_mean": e_l, "learned_max_error_per_query": per_query,
+            "pi2_pairs_at_equal_error": p_eq,
+            "pairs_ratio_pi2_over_learned": None if p_eq is None else p_eq / p_l,
+            "note": None if p_eq is not None else "learned MaxError outside the pi^2 curve's range",
+        }
+        log(f"# learned '{name}': {p_l:.3g} pairs, MaxError {e_l:.3e}; pi^2 needs "
+            f"{'n/a' if p_eq is None else f'{p_eq:.3g} pairs ({p_eq / p_l:.2f}x)'}")
+    out = {
+        "metric": "walk pairs the pi^2 rule needs at the learned allocation's MaxError (R-MAT 4.2e7, eps=1e-6)",
+        "value": out_nets["configured_workloads"]["pairs_ratio_pi2_over_learned"],
+        "unit": "ratio", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "n": g.n, "m": g.m, "c": c, "eps": eps, "sources": sources,
+                   "seeds": list(seeds), "r_scale": args.r_scale, "ref_factor": args.ref_factor,
+                   "v_floor_ratio": es.ES_LEARNED_FLOOR},
+        "pi2_curve": [{"factor": f, "max_error_mean": e, "pairs": p} for f, e, p in curve],
+        "networks": out_nets,
+    }
+    g.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def paper_budget_main(args):
     """Chung-Lu n=2,000, m=20,000, eps=1e-4 at the paper's own sample budget
     (r_scale = 1): no scaling of R anywhere, so every query is the method as
@@ -562,6 +670,8 @@ def main():
         sys.exit(2)
     if args.workload == "rmat42m":
         return learned_main(args)
+    if args.workload == "equal_error":
+        return equal_error_main(args)
     if args.workload == "cl2k":
         return paper_budget_main(args)
     if args.workload != "single":

@@ -36,6 +36,9 @@
  *  - Work is enqueued asynchronously on the context's HIP stream.  Calls that
  *    return values through host pointers synchronize that stream first.
  *  - One context per host thread; calls on one context must not overlap.
+ *    A graph handle holds the level passes' scratch (partial sums, the
+ *    binned values), so calls on one graph must not overlap either, even
+ *    from different contexts.
  *  - Node ids are int32 in [0, n); edge and sample counts are 64-bit.
  *  - Results are a pure function of the graph, the source, the options of
  *    es_query_opts and the network weights: they do not depend on launch
@@ -75,6 +78,15 @@ typedef enum {
 /* es_graph_from_edges flags */
 #define ES_DEDUP 1u            /* merge repeated (src, dst) pairs: Eq. 1 uses neighbour sets */
 #define ES_DROP_SELF_LOOPS 2u  /* drop (v, v) edges */
+/* Level pass of es_forward / es_backward (and of a whole query); with neither
+ * flag, graphs of at least 2^24 nodes take the binned pass, smaller ones the
+ * pull pass.  Both give the same pi^l bit for bit. */
+#define ES_LEVELS_PULL 4u      /* each row gathers its terms (two int32 CSRs only)          */
+#define ES_LEVELS_BINNED 8u    /* push form in bins of destination rows: the sources are
+                                  streamed, one 8-byte value per edge is written to its
+                                  bin and summed there in LDS; costs 8 + 2 x 4 bytes per
+                                  edge of device memory more and is the faster pass once
+                                  the level vectors no longer fit in the caches          */
 
 typedef struct {
   double c;                  /* decay factor, 0 < c <= 0.99 (the paper uses 0.6)            */
@@ -148,13 +160,17 @@ const char* es_last_error(const es_ctx* ctx);
  * out-CSR list O(v) (used by the forward pass P pi, pull form), rows of the
  * in-CSR list I(v) in ascending id order (walks and the backward pass
  * P^T s), plus 1/d_in(v) as float64 (Section 2: P(i,j) = 1/d_in(v_j) for
- * v_i in I(v_j)).  Errors: ES_EINVAL (id outside [0,n), NULL pointer),
- * ES_ERANGE (n < 1, n or m >= 2^31), ES_ENOMEM. */
+ * v_i in I(v_j)).  flags: ES_DEDUP, ES_DROP_SELF_LOOPS, and at most one of
+ * ES_LEVELS_PULL / ES_LEVELS_BINNED.  Errors: ES_EINVAL (id outside [0,n),
+ * NULL pointer, unknown or conflicting flags), ES_ERANGE (n < 1, n or
+ * m >= 2^31), ES_ENOMEM. */
 es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                               uint32_t flags, es_graph** out);
 es_status es_graph_destroy(es_graph* g);
 /* Node count and edge count after flags were applied (host outputs). */
 es_status es_graph_info(const es_graph* g, int32_t* n, int64_t* m);
+/* *binned (host) = 1 if the graph's level passes run binned, 0 if pull. */
+es_status es_graph_level_pass(const es_graph* g, int32_t* binned);
 /* Copy the in-degrees (device int32 [n]) and out-degrees (device int32 [n]);
  * either pointer may be NULL. */
 es_status es_graph_degrees(es_ctx* ctx, const es_graph* g, int32_t* din, int32_t* dout);
@@ -234,7 +250,14 @@ es_status es_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint
 /* Algorithm 1, back-accumulation.  levels as written by es_forward (L+1 rows),
  * D: device float64 [n]; s: device float64 [n] receives
  * s^L with s^0 = D pi^L/(1-sqrt c) and
- * s^l(j) = sqrt(c) * (1/d_in(j)) * sum_{i in I(v_j)} s^(l-1)(i) + D(j) pi^(L-l)(j)/(1-sqrt c). */
+ * s^l(j) = sqrt(c) * (1/d_in(j)) * sum_{i in I(v_j)} s^(l-1)(i) + D(j) pi^(L-l)(j)/(1-sqrt c).
+ * The sum over I(v_j) is float64 added in list order on a pull-pass graph;
+ * on a binned graph every term is rounded to a multiple of 2^-72 (ties away
+ * from zero), summed exactly in 128-bit integers and converted to float64
+ * (terms of magnitude 2^24 or more are outside its range; with D in [0, 1]
+ * and c <= 0.99 every term is below 1/(1-sqrt c)^2 < 2^16, since P^T
+ * averages).  Both orders are fixed, so a graph's results repeat bit for
+ * bit. */
 es_status es_backward(es_ctx* ctx, const es_graph* g, const double* levels, int32_t L, const double* D,
                       double c, double* s);
 

@@ -32,10 +32,12 @@ ES_LEARNED_FLOOR = 0.5  # recommended v_floor_ratio of the learned allocation
 
 ES_DEDUP = 1
 ES_DROP_SELF_LOOPS = 2
+ES_LEVELS_PULL = 4
+ES_LEVELS_BINNED = 8
 
 SYMBOLS = (
     "es_ctx_create", "es_ctx_destroy", "es_ctx_sync", "es_status_str", "es_last_error",
-    "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_degrees",
+    "es_graph_from_edges", "es_graph_destroy", "es_graph_info", "es_graph_level_pass", "es_graph_degrees",
     "es_num_levels", "es_total_samples", "es_forward", "es_budget", "es_walk_pairs", "es_diag",
     "es_backward", "es_single_source", "es_topk", "es_topk_noalloc", "es_batch", "es_batch_tuning", "es_batch_block_width",
     "es_mlp_num_params", "es_mlp_features", "es_mlp_infer", "es_mlp_grad", "es_mlp_train", "es_mlp_load",
@@ -99,6 +101,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "es_graph_from_edges": [P, i32, i64, P, P, u32, ctypes.POINTER(P)],
         "es_graph_destroy": [P],
         "es_graph_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "es_graph_level_pass": [P, ctypes.POINTER(i32)],
         "es_graph_degrees": [P, P, P, P],
         "es_num_levels": [dbl, dbl, ctypes.POINTER(i32)],
         "es_total_samples": [i32, dbl, dbl, dbl, ctypes.POINTER(dbl)],
@@ -213,6 +216,9 @@ class Graph:
         _check(lib.es_graph_info(h, ctypes.byref(nn), ctypes.byref(mm)), ctx)
         self.n = nn.value
         self.m = mm.value
+        binned = ctypes.c_int32()
+        _check(lib.es_graph_level_pass(h, ctypes.byref(binned)), ctx)
+        self.binned = bool(binned.value)
 
     def close(self):
         if self.handle:

@@ -118,6 +118,7 @@ es_status lifetime_table(es_ctx* ctx, double c) {
   ES_CHECK_HIP(ctx, hipMemcpyAsync(ctx->thr, thr.data(), sizeof(uint64_t) * (kCap + 1), hipMemcpyHostToDevice,
                                    ctx->stream));
   ES_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int q = 0; q < 16; ++q) ctx->thr_head[q] = thr[q + 1];
   ctx->tmax = tmax;
   ctx->thr_c = c;
   return ES_OK;
@@ -163,6 +164,53 @@ void free_plan(SpmvPlan* plan) {
   (void)hipFree(plan->counters);
   (void)hipFree(plan->partials);
   *plan = SpmvPlan{};
+}
+
+es_status build_binned_plan(es_ctx* ctx, const int32_t* off, const int32_t* idx, int32_t n, int32_t shift,
+                            size_t row_bytes, BinnedPlan* plan) {
+  BinnedLayout b;
+  try {
+    build_binned(off, idx, n, shift, b);
+  } catch (...) {
+    return fail(ctx, ES_ENOMEM, "binned level layout");
+  }
+  *plan = BinnedPlan{};
+  plan->shift = shift;
+  plan->nbins = b.nbins;
+  plan->nranges = (int32_t)b.ranges.size();
+  plan->nitems = (int32_t)b.items.size();
+  plan->nsplits = (int32_t)b.splits.size();
+  plan->nslots = b.nslots;
+  auto up = [&](void** dptr, const void* host, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dptr, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return e;
+    if (bytes) e = hipMemcpy(*dptr, host, bytes, hipMemcpyHostToDevice);
+    return e;
+  };
+  hipError_t e = up((void**)&plan->ranges, b.ranges.data(), sizeof(BinRange) * b.ranges.size());
+  if (e == hipSuccess) e = up((void**)&plan->src_local, b.src_local.data(), 2 * b.src_local.size());
+  if (e == hipSuccess) e = up((void**)&plan->pos, b.pos.data(), 4 * b.pos.size());
+  if (e == hipSuccess) e = up((void**)&plan->row_local, b.row_local.data(), 2 * b.row_local.size());
+  if (e == hipSuccess) e = up((void**)&plan->items, b.items.data(), sizeof(BinItem) * b.items.size());
+  if (e == hipSuccess) e = up((void**)&plan->splits, b.splits.data(), sizeof(BinSplit) * b.splits.size());
+  if (e == hipSuccess)
+    e = hipMalloc(&plan->partials, std::max<size_t>(8, (size_t)b.nslots * ((size_t)1 << shift) * row_bytes));
+  if (e != hipSuccess) {
+    free_binned_plan(plan);
+    return hip_fail(ctx, e, "binned level layout upload");
+  }
+  return ES_OK;
+}
+
+void free_binned_plan(BinnedPlan* plan) {
+  (void)hipFree(plan->ranges);
+  (void)hipFree(plan->src_local);
+  (void)hipFree(plan->pos);
+  (void)hipFree(plan->row_local);
+  (void)hipFree(plan->items);
+  (void)hipFree(plan->splits);
+  (void)hipFree(plan->partials);
+  *plan = BinnedPlan{};
 }
 
 }  // namespace es
@@ -258,6 +306,10 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
   if (!ctx || !out) return ES_EINVAL;
   *out = nullptr;
   if (n < 1 || m < 0 || m >= (int64_t)INT32_MAX) return fail(ctx, ES_ERANGE, "n=%d m=%lld", n, (long long)m);
+  if ((flags & ES_LEVELS_PULL) && (flags & ES_LEVELS_BINNED))
+    return fail(ctx, ES_EINVAL, "ES_LEVELS_PULL and ES_LEVELS_BINNED together");
+  if (flags & ~(uint32_t)(ES_DEDUP | ES_DROP_SELF_LOOPS | ES_LEVELS_PULL | ES_LEVELS_BINNED))
+    return fail(ctx, ES_EINVAL, "unknown flags 0x%x", flags);
   if (m > 0 && (!src || !dst)) return fail(ctx, ES_EINVAL, "null edge array");
   std::vector<uint64_t> keys;
   int64_t bad = -1;
@@ -316,6 +368,15 @@ es_status es_graph_from_edges(es_ctx* ctx, int32_t n, int64_t m, const int32_t* 
   g->h_in_off = h.in_off;
   es_status st = build_plan(ctx, h.out_off.data(), n, &g->fwd);
   if (st == ES_OK) st = build_plan(ctx, h.in_off.data(), n, &g->back);
+  g->binned = (flags & ES_LEVELS_BINNED) || (!(flags & ES_LEVELS_PULL) && n >= kBinnedAutoNodes);
+  if (st == ES_OK && g->binned) {
+    st = build_binned_plan(ctx, h.in_off.data(), h.in_idx.data(), n, kBinShiftFwd, 8, &g->bfwd);
+    if (st == ES_OK) st = build_binned_plan(ctx, h.out_off.data(), h.out_idx.data(), n, kBinShiftBack, 16, &g->bback);
+    if (st == ES_OK) {
+      const hipError_t he = hipMalloc(&g->bin_vals, 8 * std::max<size_t>(1, (size_t)g->m));
+      if (he != hipSuccess) st = hip_fail(ctx, he, "binned level values");
+    }
+  }
   if (st != ES_OK) {
     es_graph_destroy(g);
     return st;
@@ -344,7 +405,16 @@ es_status es_graph_destroy(es_graph* g) {
   (void)hipFree(g->lde_g);
   free_plan(&g->fwd);
   free_plan(&g->back);
+  free_binned_plan(&g->bfwd);
+  free_binned_plan(&g->bback);
+  (void)hipFree(g->bin_vals);
   delete g;
+  return ES_OK;
+}
+
+es_status es_graph_level_pass(const es_graph* g, int32_t* binned) {
+  if (!g || !binned) return ES_EINVAL;
+  *binned = g->binned ? 1 : 0;
   return ES_OK;
 }
 

@@ -352,4 +352,133 @@ void make_tiles(const std::vector<int32_t>& off, int32_t n, int32_t entry, int32
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Binned level pass layout.
+
+void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b) {
+  const int32_t m = off[n];
+  const int32_t rows = 1 << shift;
+  const uint32_t mask = (uint32_t)rows - 1u;
+  b.shift = shift;
+  b.nbins = (int32_t)(((int64_t)n + rows - 1) >> shift);
+  b.ranges.clear();
+  // 1. ranges of consecutive sources: at most kBinSrc sources and kBinEnt
+  // entries each; a source with more than kBinEnt entries is cut into ranges
+  // of its own
+  for (int32_t j = 0; j < n;) {
+    const int32_t d = off[j + 1] - off[j];
+    if (d > kBinEnt) {
+      for (int32_t e = off[j]; e < off[j + 1]; e += kBinEnt)
+        b.ranges.push_back(BinRange{j, j + 1, e, std::min(e + kBinEnt, off[j + 1]), 0, 0});
+      ++j;
+      continue;
+    }
+    const int32_t j0 = j;
+    int32_t ents = 0;
+    while (j < n && j - j0 < kBinSrc) {
+      const int32_t dj = off[j + 1] - off[j];
+      if (dj > kBinEnt || ents + dj > kBinEnt) break;
+      ents += dj;
+      ++j;
+    }
+    b.ranges.push_back(BinRange{j0, j, off[j0], off[j], 0, 0});
+  }
+  const int64_t W = (int64_t)b.ranges.size();
+  // 2. each range's entries in (bin, push-list) order: source slots, and the
+  // destination rows in that order for step 4; its segments (bin, first entry)
+  b.src_local.assign((size_t)m, 0);
+  std::vector<uint16_t> tmp_row((size_t)m, 0);
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rsegs((size_t)W);
+  par_for(W, 1, [&](int64_t lo, int64_t hi) {
+    std::vector<uint64_t> keys;
+    std::vector<uint16_t> loc;
+    for (int64_t w = lo; w < hi; ++w) {
+      const BinRange& r = b.ranges[(size_t)w];
+      const int32_t E = r.e1 - r.e0;
+      keys.resize((size_t)E);
+      loc.resize((size_t)E);
+      for (int32_t j = r.j0; j < r.j1; ++j)
+        for (int32_t e = std::max(off[j], r.e0); e < std::min(off[j + 1], r.e1); ++e)
+          loc[(size_t)(e - r.e0)] = (uint16_t)(j - r.j0);
+      for (int32_t t = 0; t < E; ++t)
+        keys[(size_t)t] = ((uint64_t)((uint32_t)idx[r.e0 + t] >> shift) << 32) | (uint32_t)t;
+      std::sort(keys.begin(), keys.end());
+      auto& sg = rsegs[(size_t)w];
+      int32_t last = -1;
+      for (int32_t t = 0; t < E; ++t) {
+        const int32_t bin = (int32_t)(keys[(size_t)t] >> 32);
+        const uint32_t el = (uint32_t)keys[(size_t)t];
+        b.src_local[(size_t)(r.e0 + t)] = loc[el];
+        tmp_row[(size_t)(r.e0 + t)] = (uint16_t)((uint32_t)idx[r.e0 + (int32_t)el] & mask);
+        if (bin != last) {
+          sg.emplace_back(bin, t);
+          last = bin;
+        }
+      }
+    }
+  });
+  // 3. bin-major offsets, then each segment's output position: within a bin,
+  // the ranges' segments in range order
+  std::vector<int64_t> cnt((size_t)b.nbins, 0);
+  int64_t nseg = 0;
+  for (int64_t w = 0; w < W; ++w) {
+    const BinRange& r = b.ranges[(size_t)w];
+    const auto& sg = rsegs[(size_t)w];
+    for (size_t i = 0; i < sg.size(); ++i) {
+      const int32_t end = i + 1 < sg.size() ? sg[i + 1].second : r.e1 - r.e0;
+      cnt[(size_t)sg[i].first] += end - sg[i].second;
+    }
+    nseg += (int64_t)sg.size();
+  }
+  b.bin_off.assign((size_t)b.nbins + 1, 0);
+  for (int32_t k = 0; k < b.nbins; ++k) b.bin_off[(size_t)k + 1] = b.bin_off[(size_t)k] + (int32_t)cnt[(size_t)k];
+  std::vector<int32_t> run(b.bin_off.begin(), b.bin_off.end() - 1);
+  b.segs.clear();
+  b.segs.reserve((size_t)nseg);
+  for (int64_t w = 0; w < W; ++w) {
+    BinRange& r = b.ranges[(size_t)w];
+    const auto& sg = rsegs[(size_t)w];
+    r.s0 = (int32_t)b.segs.size();
+    for (size_t i = 0; i < sg.size(); ++i) {
+      const int32_t end = i + 1 < sg.size() ? sg[i + 1].second : r.e1 - r.e0;
+      b.segs.push_back(BinSeg{(uint32_t)(r.e0 + sg[i].second), (uint32_t)run[(size_t)sg[i].first]});
+      run[(size_t)sg[i].first] += end - sg[i].second;
+    }
+    r.s1 = (int32_t)b.segs.size();
+    std::vector<std::pair<int32_t, int32_t>>().swap(rsegs[(size_t)w]);
+  }
+  // 4. destination rows in bin-major order, each entry's value position
+  b.row_local.assign((size_t)m, 0);
+  b.pos.assign((size_t)m, 0);
+  par_for(W, 1, [&](int64_t lo, int64_t hi) {
+    for (int64_t w = lo; w < hi; ++w) {
+      const BinRange& r = b.ranges[(size_t)w];
+      for (int32_t s = r.s0; s < r.s1; ++s) {
+        const uint32_t k = b.segs[(size_t)s].k, out = b.segs[(size_t)s].out;
+        const uint32_t end = s + 1 < r.s1 ? b.segs[(size_t)s + 1].k : (uint32_t)r.e1;
+        std::memcpy(&b.row_local[out], &tmp_row[k], sizeof(uint16_t) * (end - k));
+        for (uint32_t t = k; t < end; ++t) b.pos[t] = out + (t - k);
+      }
+    }
+  });
+  // 5. accumulate items: one per bin, or one per kBinAccEnt entries with a
+  // partial-sum slot each
+  b.items.clear();
+  b.splits.clear();
+  b.nslots = 0;
+  for (int32_t k = 0; k < b.nbins; ++k) {
+    const int32_t p0 = b.bin_off[(size_t)k], p1 = b.bin_off[(size_t)k + 1];
+    if (p1 - p0 <= kBinAccEnt) {
+      b.items.push_back(BinItem{k, p0, p1, -1});
+      continue;
+    }
+    const int32_t ns = (int32_t)(((int64_t)p1 - p0 + kBinAccEnt - 1) / kBinAccEnt);
+    b.splits.push_back(BinSplit{k, b.nslots, ns});
+    for (int32_t t = 0; t < ns; ++t)
+      b.items.push_back(BinItem{k, p0 + t * kBinAccEnt, std::min(p1, p0 + (t + 1) * kBinAccEnt), b.nslots + t});
+    b.nslots += ns;
+  }
+}
+
 }  // namespace es

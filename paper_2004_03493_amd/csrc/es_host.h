@@ -73,6 +73,67 @@ void par_sort(std::vector<uint64_t>& a);
 bool pack_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, bool drop_self_loops, bool dedup,
                 std::vector<uint64_t>& keys, int64_t* bad);
 
+// Binned (propagation-blocked) level pass: the level product is computed in
+// push form.  A scatter pass streams the sources in order, each workgroup
+// staging the values of one range of sources and writing one value per edge
+// into the bin of the edge's destination row; an accumulate pass then sums
+// each bin's values into its rows in LDS.  Every access to the level vectors
+// is a sequential one; the per-edge traffic is a 2-byte source slot and a
+// 4-byte position, the 8-byte value written and read back, and a 2-byte row
+// slot.
+#ifndef ES_BIN_SRC
+#define ES_BIN_SRC 8192
+#endif
+#ifndef ES_BIN_ENT
+#define ES_BIN_ENT (1 << 18)
+#endif
+#ifndef ES_BIN_ACC_ENT
+#define ES_BIN_ACC_ENT (1 << 18)
+#endif
+constexpr int kBinSrc = ES_BIN_SRC;        // sources staged per scatter workgroup (64 KiB of values)
+constexpr int kBinEnt = ES_BIN_ENT;        // entries per scatter workgroup
+constexpr int kBinAccEnt = ES_BIN_ACC_ENT; // entries per accumulate workgroup (larger bins are split)
+
+struct BinRange {
+  int32_t j0, j1;  // sources [j0, j1) (one source when its list is cut into several ranges)
+  int32_t e0, e1;  // its entries [e0, e1) in push-list order
+  int32_t s0, s1;  // its segments (one per bin it writes), ascending bin
+};
+
+struct BinSeg {
+  uint32_t k;    // first entry of the segment (absolute, within [e0, e1) of its range)
+  uint32_t out;  // position of that entry's value in the bin-major value array
+};
+
+struct BinItem {
+  int32_t bin;
+  int32_t p0, p1;  // bin-major entries [p0, p1)
+  int32_t slot;    // -1: the item completes the bin; else its partial-sum slot
+};
+
+struct BinSplit {
+  int32_t bin;
+  int32_t slot0, nslot;  // partial-sum slots of a bin split over several items
+};
+
+struct BinnedLayout {
+  int32_t shift = 0;  // rows per bin = 2^shift
+  int32_t nbins = 0;
+  int32_t nslots = 0;
+  std::vector<BinRange> ranges;
+  std::vector<BinSeg> segs;
+  std::vector<uint16_t> src_local;  // [m] source - j0 of each entry, each range's entries in bin order
+  std::vector<uint32_t> pos;        // [m] each entry's position in the bin-major value array
+  std::vector<uint16_t> row_local;  // [m] destination row - bin * 2^shift, bin-major
+  std::vector<int32_t> bin_off;     // [nbins + 1] bin-major offsets
+  std::vector<BinItem> items;       // every bin has at least one item (its rows are written even when empty)
+  std::vector<BinSplit> splits;
+};
+
+// Push lists: source j sends to idx[off[j] .. off[j+1]) (destination rows in
+// [0, n)); shift in [1, 16].
+void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b);
+
 // Degree-ordered relabelling and the two CSR copies under internal ids.
 // keys: edges (src << 32 | dst) in external ids, sorted ascending, distinct
 // or not (every key is one edge).

@@ -40,6 +40,19 @@ struct SpmvPlan {
   int32_t max_row_nnz = 0;
 };
 
+// Binned level pass of one direction (push form; the layout is built on the
+// host by build_binned): device copies plus the partial sums of split bins.
+struct BinnedPlan {
+  int32_t shift = 0, nbins = 0, nranges = 0, nitems = 0, nsplits = 0, nslots = 0;
+  BinRange* ranges = nullptr;
+  uint16_t* src_local = nullptr;
+  uint32_t* pos = nullptr;
+  uint16_t* row_local = nullptr;
+  BinItem* items = nullptr;
+  BinSplit* splits = nullptr;
+  void* partials = nullptr;  // [nslots x 2^shift] row sums (8 or 16 bytes each)
+};
+
 struct BatchPlan;
 
 // Source-independent sums of a node's transition tables (Algorithm 3's level
@@ -100,6 +113,12 @@ struct es_graph {
   std::vector<std::pair<int32_t, int32_t>> tuned_block;
   es::SpmvPlan fwd;            // over the out-CSR
   es::SpmvPlan back;           // over the in-CSR
+  // binned level pass (graphs too large for the caches, or on request):
+  // forward pushes along the in-lists, backward along the out-lists; one
+  // 8-byte value per edge in between
+  bool binned = false;
+  es::BinnedPlan bfwd, bback;
+  void* bin_vals = nullptr;    // [m] x 8 bytes
   // learned allocation: predicted variances v(k) by internal id for the
   // network identified by vhat_net at decay vhat_c (features and network
   // are source-independent, so one prediction serves every query)
@@ -124,6 +143,7 @@ struct es_ctx {
   std::vector<size_t> ws_bytes;
   // walk lifetime thresholds for the cached decay factor
   uint64_t* thr = nullptr;
+  uint64_t thr_head[16] = {};  // host copy of thresholds 1..16 (zeros past tmax)
   int32_t tmax = 0;
   double thr_c = -1.0;
   hipEvent_t ev[8] = {};
@@ -287,6 +307,24 @@ es_status topk_scratch_init(es_ctx* ctx);
 es_status build_plan(es_ctx* ctx, const int32_t* off_host, int32_t n, SpmvPlan* plan);
 void free_batch_plans(es_ctx* ctx);
 void free_plan(SpmvPlan* plan);
+// Binned layout of the push lists (off, idx) uploaded with partial-sum room
+// of row_bytes per row of every split bin.
+es_status build_binned_plan(es_ctx* ctx, const int32_t* off, const int32_t* idx, int32_t n, int32_t shift,
+                            size_t row_bytes, BinnedPlan* plan);
+void free_binned_plan(BinnedPlan* plan);
+// rows per bin of the two directions: 2^13 int64 sums (forward), 2^12
+// 128-bit sums (backward), 64 KiB of LDS each
+#ifndef ES_BIN_SHIFT_FWD
+#define ES_BIN_SHIFT_FWD 13
+#endif
+#ifndef ES_BIN_SHIFT_BACK
+#define ES_BIN_SHIFT_BACK 12
+#endif
+constexpr int32_t kBinShiftFwd = ES_BIN_SHIFT_FWD;
+constexpr int32_t kBinShiftBack = ES_BIN_SHIFT_BACK;
+// graphs with at least this many nodes take the binned pass unless the
+// caller asks for the pull pass
+constexpr int32_t kBinnedAutoNodes = 1 << 24;
 
 // host constants
 int32_t num_levels(double c, double eps);

@@ -206,6 +206,238 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
   }
 }
 
+// ---- binned level pass (push form) ----------------------------------------
+//
+// Scatter: one workgroup per range of sources stages their values in LDS and
+// writes each entry's value to its position in the bin-major array (runs of
+// consecutive positions, one per bin the range reaches).  Accumulate: one workgroup
+// per item sums its entries into the bin's rows in LDS (int64 forward; 128-bit
+// fixed point backward, so the sums are exact and the order of the atomics
+// does not matter), then applies the epilogue, or stores partial sums when
+// the bin is split over several items; a combine launch adds those in slot
+// order.
+
+constexpr int kBinThreads = 1024;
+#ifndef ES_BIN_SCATTER_UNROLL
+#define ES_BIN_SCATTER_UNROLL 4
+#endif
+#ifndef ES_BIN_ACC_UNROLL
+#define ES_BIN_ACC_UNROLL 4
+#endif
+constexpr int kFixBits = 72;  // backward terms as multiples of 2^-72
+constexpr double kFixB = 0x1p72;
+constexpr double kFixBInv = 0x1p-72;
+
+template <class V>
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const BinRange* __restrict__ ranges,
+                                                                  const uint16_t* __restrict__ src_local,
+                                                                  const uint32_t* __restrict__ pos,
+                                                                  const V* __restrict__ x, V* __restrict__ vals) {
+  __shared__ V xs[kBinSrc];
+  const BinRange r = ranges[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < r.j1 - r.j0; t += kBinThreads) xs[t] = x[r.j0 + t];
+  __syncthreads();
+  constexpr int kU = ES_BIN_SCATTER_UNROLL;
+  for (int k = r.e0 + tid; k < r.e1; k += kU * kBinThreads) {
+    uint32_t sl[kU], ps[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = min(k + u * kBinThreads, r.e1 - 1);
+      sl[u] = src_local[q];
+      ps[u] = pos[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k + u * kBinThreads < r.e1) vals[ps[u]] = xs[sl[u]];
+  }
+}
+
+// forward: exact int64 sums of the bin's rows
+template <class Epi>
+__global__ __launch_bounds__(kBinThreads) void bin_acc_fwd_kernel(const BinItem* __restrict__ items,
+                                                                  const uint16_t* __restrict__ row_local,
+                                                                  const int64_t* __restrict__ vals, int32_t n,
+                                                                  Epi epi, int64_t* __restrict__ partials) {
+  constexpr int kRows = 1 << kBinShiftFwd;
+  __shared__ unsigned long long acc[kRows];
+  const BinItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < kRows; t += kBinThreads) acc[t] = 0ull;
+  __syncthreads();
+  constexpr int kU = ES_BIN_ACC_UNROLL;
+  for (int p = it.p0 + tid; p < it.p1; p += kU * kBinThreads) {
+    uint32_t rr[kU];
+    unsigned long long v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = min(p + u * kBinThreads, it.p1 - 1);
+      rr[u] = row_local[q];
+      v[u] = (unsigned long long)vals[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (p + u * kBinThreads < it.p1) atomicAdd(&acc[rr[u]], v[u]);
+  }
+  __syncthreads();
+  const int32_t r0 = it.bin << kBinShiftFwd;
+  const int nr = min(n - r0, kRows);
+  if (it.slot < 0) {
+    for (int t = tid; t < nr; t += kBinThreads) epi.apply(r0 + t, (int64_t)acc[t], epi.load(r0 + t));
+  } else {
+    int64_t* dst = partials + (size_t)it.slot * kRows;
+    for (int t = tid; t < nr; t += kBinThreads) dst[t] = (int64_t)acc[t];
+  }
+}
+
+template <class Epi>
+__global__ void bin_combine_fwd_kernel(const BinSplit* __restrict__ splits, int32_t n, Epi epi,
+                                       const int64_t* __restrict__ partials) {
+  constexpr int kRows = 1 << kBinShiftFwd;
+  constexpr int kPer = kRows / 256;
+  const BinSplit sp = splits[blockIdx.x / kPer];
+  const int t = (blockIdx.x % kPer) * 256 + threadIdx.x;
+  const int32_t r = (sp.bin << kBinShiftFwd) + t;
+  if (r >= n) return;
+  int64_t acc = 0;
+  for (int q = 0; q < sp.nslot; ++q) acc += partials[(size_t)(sp.slot0 + q) * kRows + t];
+  epi.apply(r, acc, epi.load(r));
+}
+
+// v as a 128-bit two's-complement multiple of 2^-72, rounded half away from
+// zero; zero for |v| < 2^-1022 (never a term above the rounding)
+__device__ __forceinline__ void to_fixed(double v, unsigned long long& lo, unsigned long long& hi) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const int e = (int)((bits >> 52) & 0x7ff);
+  lo = 0ull;
+  hi = 0ull;
+  if (e == 0) return;
+  const unsigned long long m = (bits & 0xfffffffffffffull) | (1ull << 52);
+  const int sh = e - 1075 + kFixBits;
+  if (sh >= 64) {
+    hi = m << (sh - 64);
+  } else if (sh > 0) {
+    lo = m << sh;
+    hi = m >> (64 - sh);
+  } else if (sh == 0) {
+    lo = m;
+  } else if (sh > -64) {
+    lo = (m + (1ull << (-sh - 1))) >> (-sh);
+  }
+  if (bits >> 63) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+}
+
+__device__ __forceinline__ double from_fixed(unsigned long long lo, unsigned long long hi) {
+  const bool neg = (long long)hi < 0;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const double d = ((double)hi * 0x1p64 + (double)lo) * kFixBInv;
+  return neg ? -d : d;
+}
+
+// backward: exact 128-bit sums of the bin's rows (low words with their carries
+// passed on to the high words)
+template <class Epi>
+__global__ __launch_bounds__(kBinThreads) void bin_acc_back_kernel(const BinItem* __restrict__ items,
+                                                                   const uint16_t* __restrict__ row_local,
+                                                                   const double* __restrict__ vals, int32_t n,
+                                                                   Epi epi,
+                                                                   unsigned long long* __restrict__ partials) {
+  constexpr int kRows = 1 << kBinShiftBack;
+  __shared__ unsigned long long alo[kRows];
+  __shared__ unsigned long long ahi[kRows];
+  const BinItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < kRows; t += kBinThreads) {
+    alo[t] = 0ull;
+    ahi[t] = 0ull;
+  }
+  __syncthreads();
+  constexpr int kU = ES_BIN_ACC_UNROLL;
+  for (int p = it.p0 + tid; p < it.p1; p += kU * kBinThreads) {
+    uint32_t rr[kU];
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = min(p + u * kBinThreads, it.p1 - 1);
+      rr[u] = row_local[q];
+      v[u] = vals[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (p + u * kBinThreads < it.p1) {
+        unsigned long long xl, xh;
+        to_fixed(v[u], xl, xh);
+        const unsigned long long old = atomicAdd(&alo[rr[u]], xl);
+        const unsigned long long up = xh + (old + xl < old ? 1ull : 0ull);
+        if (up) atomicAdd(&ahi[rr[u]], up);
+      }
+    }
+  }
+  __syncthreads();
+  const int32_t r0 = it.bin << kBinShiftBack;
+  const int nr = min(n - r0, kRows);
+  if (it.slot < 0) {
+    for (int t = tid; t < nr; t += kBinThreads) epi.apply(r0 + t, from_fixed(alo[t], ahi[t]), epi.load(r0 + t));
+  } else {
+    unsigned long long* dst = partials + (size_t)it.slot * kRows * 2;
+    for (int t = tid; t < nr; t += kBinThreads) {
+      dst[2 * t] = alo[t];
+      dst[2 * t + 1] = ahi[t];
+    }
+  }
+}
+
+template <class Epi>
+__global__ void bin_combine_back_kernel(const BinSplit* __restrict__ splits, int32_t n, Epi epi,
+                                        const unsigned long long* __restrict__ partials) {
+  constexpr int kRows = 1 << kBinShiftBack;
+  constexpr int kPer = kRows / 256;
+  const BinSplit sp = splits[blockIdx.x / kPer];
+  const int t = (blockIdx.x % kPer) * 256 + threadIdx.x;
+  const int32_t r = (sp.bin << kBinShiftBack) + t;
+  if (r >= n) return;
+  unsigned long long lo = 0ull, hi = 0ull;
+  for (int q = 0; q < sp.nslot; ++q) {
+    const unsigned long long* p = partials + ((size_t)(sp.slot0 + q) * kRows + t) * 2;
+    const unsigned long long pl = p[0];
+    lo += pl;
+    hi += p[1] + (lo < pl ? 1ull : 0ull);
+  }
+  epi.apply(r, from_fixed(lo, hi), epi.load(r));
+}
+
+template <class Epi>
+void binned_forward_level(es_ctx* ctx, const es_graph* g, const int64_t* q, const Epi& ep) {
+  const BinnedPlan& b = g->bfwd;
+  int64_t* vals = (int64_t*)g->bin_vals;
+  if (b.nranges > 0)
+    bin_scatter_kernel<int64_t><<<b.nranges, kBinThreads, 0, ctx->stream>>>(b.ranges, b.src_local, b.pos, q, vals);
+  bin_acc_fwd_kernel<Epi><<<b.nitems, kBinThreads, 0, ctx->stream>>>(b.items, b.row_local, vals, g->n, ep,
+                                                                     (int64_t*)b.partials);
+  if (b.nsplits > 0)
+    bin_combine_fwd_kernel<Epi><<<b.nsplits * ((1 << kBinShiftFwd) / 256), 256, 0, ctx->stream>>>(
+        b.splits, g->n, ep, (const int64_t*)b.partials);
+}
+
+template <class Epi>
+void binned_backward_level(es_ctx* ctx, const es_graph* g, const double* s, const Epi& ep) {
+  const BinnedPlan& b = g->bback;
+  double* vals = (double*)g->bin_vals;
+  if (b.nranges > 0)
+    bin_scatter_kernel<double><<<b.nranges, kBinThreads, 0, ctx->stream>>>(b.ranges, b.src_local, b.pos, s, vals);
+  bin_acc_back_kernel<Epi><<<b.nitems, kBinThreads, 0, ctx->stream>>>(b.items, b.row_local, vals, g->n, ep,
+                                                                      (unsigned long long*)b.partials);
+  if (b.nsplits > 0)
+    bin_combine_back_kernel<Epi><<<b.nsplits * ((1 << kBinShiftBack) / 256), 256, 0, ctx->stream>>>(
+        b.splits, g->n, ep, (const unsigned long long*)b.partials);
+}
+
 // pi^0 = (1 - sqrt c) e_u, q^0 = round(pi^0 / d_in * 2^62)
 __global__ void forward_init_kernel(int32_t n, int32_t u, double pi0, const double* __restrict__ inv_din,
                                     double* __restrict__ lvl0, int64_t* __restrict__ q0) {
@@ -427,7 +659,9 @@ es_status launch_forward(es_ctx* ctx, const es_graph* g, int32_t u, double c, in
   for (int32_t l = 1; l <= L; ++l) {
     FwdGather ga{qp};
     FwdEpi ep{sc, g->inv_din, slot(l), qn};
-    if (g->fwd.nblocks > 0)
+    if (g->binned)
+      binned_forward_level(ctx, g, qp, ep);
+    else if (g->fwd.nblocks > 0)
       spmv_pull_kernel<int64_t, FwdGather, FwdEpi><<<g->fwd.nblocks, kSpmvThreads, 0, ctx->stream>>>(
           g->fwd.blocks, g->out_off, g->out_idx, ga, ep, (int64_t*)g->fwd.partials, g->fwd.long_p0, g->fwd.long_nch,
           g->fwd.counters);
@@ -458,7 +692,9 @@ es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, 
     for (int32_t l = 1; l <= L; ++l) {
       BackGather ga{cur};
       BackEpiSparse ep{sc, g->inv_din, nxt};
-      if (g->back.nblocks > 0)
+      if (g->binned)
+        binned_backward_level(ctx, g, cur, ep);
+      else if (g->back.nblocks > 0)
         spmv_pull_kernel<double, BackGather, BackEpiSparse><<<g->back.nblocks, kSpmvThreads, 0, ctx->stream>>>(
             g->back.blocks, g->in_off, g->in_idx, ga, ep, (double*)g->back.partials, g->back.long_p0,
             g->back.long_nch, g->back.counters);
@@ -472,7 +708,9 @@ es_status launch_backward(es_ctx* ctx, const es_graph* g, const double* levels, 
   for (int32_t l = 1; l <= L; ++l) {
     BackGather ga{cur};
     BackEpi ep{sc, a, g->inv_din, D, levels + (int64_t)(L - l) * n, nxt};
-    if (g->back.nblocks > 0)
+    if (g->binned)
+      binned_backward_level(ctx, g, cur, ep);
+    else if (g->back.nblocks > 0)
       spmv_pull_kernel<double, BackGather, BackEpi><<<g->back.nblocks, kSpmvThreads, 0, ctx->stream>>>(
           g->back.blocks, g->in_off, g->in_idx, ga, ep, (double*)g->back.partials, g->back.long_p0,
           g->back.long_nch, g->back.counters);

@@ -24,7 +24,11 @@ constexpr int kScanBlock = kScanThreads * kScanPer;  // nodes per scan block
 constexpr int kWalkThreads = 256;
 constexpr uint64_t kWalkMinRun = 16;    // samples per lane per chunk, lower and upper bound
 constexpr uint64_t kWalkMaxRun = 1024;
-constexpr int kLifeRegs = 8;            // lifetime thresholds kept in registers
+#ifndef ES_LIFE_REGS
+#define ES_LIFE_REGS 8
+#endif
+constexpr int kLifeRegs = ES_LIFE_REGS;  // leading lifetime thresholds passed by value (scalar registers)
+static_assert(kLifeRegs >= 1 && kLifeRegs <= 16, "es_ctx keeps 16 leading thresholds");
 
 __global__ void budget_kernel(int32_t n, const double* __restrict__ pi, const int32_t* __restrict__ din_arr,
                               double R, int32_t alloc, int32_t exact_small_din, const float* __restrict__ vhat,
@@ -311,6 +315,7 @@ struct WalkArgs {
   const int32_t* __restrict__ to_graph;   // count index -> internal id (NULL: identity)
   const int32_t* __restrict__ to_stream;  // count index -> external id (NULL: identity)
   const uint64_t* __restrict__ thr;
+  uint64_t head[kLifeRegs];  // thr[1..kLifeRegs]
   int32_t tmax;
   WalkTotals* tot;
   unsigned long long* __restrict__ M;  // per count index; with buckets: [index * B + bucket]
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
   auto lifetime = [&](uint64_t u) -> uint32_t {
     uint32_t T = 0;
 #pragma unroll
-    for (int q = 1; q <= kLifeRegs; ++q) T += u < a.thr[q] ? 1u : 0u;  // thresholds decrease
+    for (int q = 1; q <= kLifeRegs; ++q) T += u < a.head[q - 1] ? 1u : 0u;  // thresholds decrease
     if (T == kLifeRegs)
       while ((int32_t)T < a.tmax && u < a.thr[T + 1]) ++T;
     return T;
@@ -612,6 +617,7 @@ es_status walks_core(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, co
   a.to_graph = external_counts ? g->int_of : nullptr;
   a.to_stream = external_counts ? nullptr : g->ext_of;
   a.thr = ctx->thr;
+  for (int q = 0; q < kLifeRegs; ++q) a.head[q] = ctx->thr_head[q];
   a.tmax = ctx->tmax;
   a.tot = tot;
   a.M = M;

@@ -1,9 +1,11 @@
 // Runs the library's host-side builders (es_host.cpp: edge packing, the
-// degree-ordered CSR layout, the SpMV row partition and the batched SpMM
-// tiles) on edge cases, with invariant checks, so that a build with
-// AddressSanitizer and UndefinedBehaviorSanitizer checks every access:
+// degree-ordered CSR layout, the SpMV row partition, the batched SpMM tiles
+// and the binned level pass layout) on edge cases, with invariant checks, so
+// that a build with AddressSanitizer and UndefinedBehaviorSanitizer checks
+// every access:
 // one node, no edges, duplicate edges and self-loops, rows longer than the
-// SpMV's 8192-entry and the SpMM's 1024-entry cuts, an id out of range.
+// SpMV's 8192-entry and the SpMM's 1024-entry cuts, push lists and bins
+// longer than the binned level pass's ranges and items, an id out of range.
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
@@ -93,6 +95,82 @@ static int check_tiles(const std::vector<int32_t>& off, int32_t n) {
   return 0;
 }
 
+// Binned layout: every edge appears once as (source, destination row), every
+// value position once, ranges and items within their limits and in order.
+static int check_binned(const std::vector<int32_t>& off, const std::vector<int32_t>& idx, int32_t n, int32_t shift) {
+  BinnedLayout b;
+  build_binned(off.data(), idx.data(), n, shift, b);
+  const int32_t m = off[n];
+  CHECK(b.nbins == (int32_t)(((int64_t)n + (1 << shift) - 1) >> shift));
+  CHECK((int32_t)b.bin_off.size() == b.nbins + 1 && b.bin_off[0] == 0 && b.bin_off[b.nbins] == m);
+  CHECK((int32_t)b.src_local.size() == m && (int32_t)b.row_local.size() == m && (int32_t)b.pos.size() == m);
+  std::vector<uint64_t> want, got;
+  for (int32_t j = 0; j < n; ++j)
+    for (int32_t e = off[j]; e < off[j + 1]; ++e) want.push_back(((uint64_t)j << 32) | (uint32_t)idx[e]);
+  std::vector<uint8_t> hit((size_t)m, 0);
+  int32_t next_e = 0, next_j = 0;
+  for (const BinRange& r : b.ranges) {
+    CHECK(r.e0 == next_e && r.e0 <= r.e1 && r.e1 - r.e0 <= kBinEnt);
+    CHECK(r.j0 < r.j1 && r.j1 - r.j0 <= kBinSrc && r.j1 <= n);
+    CHECK(r.j0 == next_j || (r.j0 == next_j - 1 && r.j1 == r.j0 + 1));  // cut lists repeat their source
+    CHECK(r.e0 >= off[r.j0] && r.e1 <= off[r.j1]);
+    next_e = r.e1;
+    next_j = r.j1;
+    CHECK(r.s0 <= r.s1 && r.s1 <= (int32_t)b.segs.size());
+    CHECK((r.e1 > r.e0) == (r.s1 > r.s0));
+    int32_t last_bin = -1;
+    for (int32_t s = r.s0; s < r.s1; ++s) {
+      const BinSeg& g = b.segs[(size_t)s];
+      const uint32_t end = s + 1 < r.s1 ? b.segs[(size_t)s + 1].k : (uint32_t)r.e1;
+      CHECK(g.k >= (uint32_t)r.e0 && g.k < end && end <= (uint32_t)r.e1);
+      if (s == r.s0) CHECK(g.k == (uint32_t)r.e0);
+      const int32_t bin = (int32_t)(std::upper_bound(b.bin_off.begin(), b.bin_off.end(), (int32_t)g.out) -
+                                    b.bin_off.begin()) - 1;
+      CHECK(bin > last_bin && bin < b.nbins);
+      last_bin = bin;
+      CHECK(g.out + (end - g.k) <= (uint32_t)b.bin_off[(size_t)bin + 1]);
+      for (uint32_t k = g.k; k < end; ++k) {
+        const uint32_t pos = g.out + (k - g.k);
+        CHECK(b.pos[k] == pos);
+        CHECK(hit[pos] == 0);
+        hit[pos] = 1;
+        const int32_t j = r.j0 + b.src_local[k];
+        CHECK(j < r.j1);
+        const int64_t row = ((int64_t)bin << shift) | b.row_local[pos];
+        CHECK(row < n);
+        got.push_back(((uint64_t)j << 32) | (uint32_t)row);
+      }
+    }
+  }
+  CHECK(next_e == m && (m == 0 || next_j == n || off[next_j] == m));
+  std::sort(want.begin(), want.end());
+  std::sort(got.begin(), got.end());
+  CHECK(want == got);
+  // items: each bin's entries exactly once, in order; split bins own their slots
+  int32_t it = 0, slots = 0;
+  size_t sp = 0;
+  for (int32_t bin = 0; bin < b.nbins; ++bin) {
+    int32_t p = b.bin_off[(size_t)bin];
+    int32_t count = 0;
+    while (it < (int32_t)b.items.size() && b.items[(size_t)it].bin == bin) {
+      const BinItem& x = b.items[(size_t)it];
+      CHECK(x.p0 == p && x.p0 <= x.p1 && x.p1 - x.p0 <= kBinAccEnt);
+      p = x.p1;
+      ++count;
+      ++it;
+      if (x.slot >= 0) CHECK(x.slot == slots++);
+    }
+    CHECK(count >= 1 && p == b.bin_off[(size_t)bin + 1]);
+    if (count > 1) {
+      CHECK(sp < b.splits.size() && b.splits[sp].bin == bin && b.splits[sp].nslot == count);
+      CHECK(b.splits[sp].slot0 + count == slots);
+      ++sp;
+    }
+  }
+  CHECK(it == (int32_t)b.items.size() && sp == b.splits.size() && slots == b.nslots);
+  return 0;
+}
+
 static int run(const char* name, int32_t n, const std::vector<int32_t>& src, const std::vector<int32_t>& dst,
                bool drop, bool dedup) {
   std::vector<uint64_t> keys;
@@ -138,6 +216,8 @@ static int run(const char* name, int32_t n, const std::vector<int32_t>& src, con
   CHECK(rebuilt == keys);
   if (check_partition(h.out_off, n) || check_partition(h.in_off, n)) return 1;
   if (check_tiles(h.out_off, n) || check_tiles(h.in_off, n)) return 1;
+  for (int32_t shift : {1, 4, 13})
+    if (check_binned(h.in_off, h.in_idx, n, shift) || check_binned(h.out_off, h.out_idx, n, shift)) return 1;
   std::printf("%s: n=%d m=%lld ok\n", name, n, (long long)m);
   return 0;
 }
@@ -191,6 +271,19 @@ int main() {
       d[i] = (int32_t)((rng() % 7 == 0) ? s[i] : rng() % 64);  // self-loops, and 64 hubs of in-degree ~3e4
     }
     rc |= run("2.5e6 unsorted edges", n, s, d, true, true);
+  }
+  {
+    // a node with more in- and out-neighbours than a scatter range and an
+    // accumulate item take: cut push lists, split bins
+    const int32_t n = 300001;
+    std::vector<int32_t> s, d;
+    for (int32_t v = 1; v < n; ++v) {
+      s.push_back(v);
+      d.push_back(0);
+      s.push_back(0);
+      d.push_back(v);
+    }
+    rc |= run("star of 3e5 leaves both ways", n, s, d, true, true);
   }
   {
     // an endpoint out of range is reported, not read past
