@@ -287,8 +287,9 @@ def batch_main(args):
 def rmat42m_block(args, r_scale, steps, warmup, accuracy):
     """R-MAT n=4.2e7, m=1.4e9: the learned walk budget against the pi^2 rule.
 
-    The budget network is trained on the GPU from walk estimates on small
-    training graphs (none of them the evaluation graph).  Both allocations
+    The budget network is trained on the GPU from the method's own walk
+    estimates on the configured smaller workloads (Chung-Lu 2,000, R-MAT
+    2^20, R-MAT 4.8e6; none of them the evaluation graph).  Both allocations
     are timed on the same sources at the same r_scale; their accuracy is
     the MaxError against a pi^2 run with --ref-factor times the budget and
     another walk seed, at equal total pairs.  Algorithm 3 (reduced) and sparse
@@ -305,7 +306,7 @@ def rmat42m_block(args, r_scale, steps, warmup, accuracy):
     ctx = es.Context(0)
     t0 = time.time()
     Fs, Rs, Ms = [], [], []
-    specs = [("rmat", 1 << 16, 33 << 16, 601), ("rmat", 1 << 18, 33 << 18, 602), ("chung_lu", 1 << 16, 20 << 16, 603)]
+    specs = train_sets(workloads)["configured_workloads"]
     for i, (kind, n, m, seed) in enumerate(specs):
         s_, d_ = workloads.rmat(n, m, seed) if kind == "rmat" else workloads.chung_lu(n, m, seed)
         gt = es.Graph(ctx, n, s_, d_)
@@ -439,6 +440,20 @@ def learned_main(args):
     print(json.dumps(out), flush=True)
 
 
+def train_sets(workloads):
+    """Graphs whose method-produced D estimates train the budget network:
+    the configured smaller workloads (Chung-Lu 2,000, R-MAT 2^20, R-MAT
+    4.8e6), and for comparison three other graphs of the same families."""
+    return {
+        "configured_workloads": [("chung_lu", workloads.CHUNG_LU_2K.n, workloads.CHUNG_LU_2K.m,
+                                  workloads.CHUNG_LU_2K.seed_graph),
+                                 ("rmat", workloads.RMAT_1M.n, workloads.RMAT_1M.m, workloads.RMAT_1M.seed_graph),
+                                 ("rmat", workloads.RMAT_4M8.n, workloads.RMAT_4M8.m, workloads.RMAT_4M8.seed_graph)],
+        "other_graphs": [("rmat", 1 << 16, 33 << 16, 601), ("rmat", 1 << 18, 33 << 18, 602),
+                         ("chung_lu", 1 << 16, 20 << 16, 603)],
+    }
+
+
 def equal_error_main(args):
     """R-MAT n=4.2e7, m=1.4e9: the walk pairs the pi^2 rule needs to reach the
     learned allocation's MaxError.  MaxError against a pi^2 run with
@@ -459,16 +474,8 @@ def equal_error_main(args):
     wl = workloads.RMAT_42M
     c, eps = wl.c, wl.eps
     ctx = es.Context(0)
-    train_sets = {
-        "configured_workloads": [("chung_lu", workloads.CHUNG_LU_2K.n, workloads.CHUNG_LU_2K.m,
-                                  workloads.CHUNG_LU_2K.seed_graph),
-                                 ("rmat", workloads.RMAT_1M.n, workloads.RMAT_1M.m, workloads.RMAT_1M.seed_graph),
-                                 ("rmat", workloads.RMAT_4M8.n, workloads.RMAT_4M8.m, workloads.RMAT_4M8.seed_graph)],
-        "other_graphs": [("rmat", 1 << 16, 33 << 16, 601), ("rmat", 1 << 18, 33 << 18, 602),
-                         ("chung_lu", 1 << 16, 20 << 16, 603)],
-    }
     nets = {}
-    for name, specs in train_sets.items():
+    for name, specs in train_sets(workloads).items():
         t0 = time.time()
         Fs, Rs, Ms = [], [], []
         for kind, n, m, seed in specs:
@@ -657,7 +664,7 @@ def L_of(stats):
     return int(stats[0]["L"] if isinstance(stats[0], dict) else stats[0].L)
 
 
-BLOCK_COST_S = {"paper_budget": 20.0, "batch64": 70.0, "uneven": 160.0, "rmat42m": 130.0}
+BLOCK_COST_S = {"paper_budget": 20.0, "batch64": 70.0, "uneven": 160.0, "rmat42m": 160.0}
 
 
 def main():

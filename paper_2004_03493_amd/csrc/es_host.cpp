@@ -356,29 +356,30 @@ void make_tiles(const std::vector<int32_t>& off, int32_t n, int32_t entry, int32
 // ---------------------------------------------------------------------------
 // Binned level pass layout.
 
-void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b) {
+void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b,
+                  int32_t max_src, int32_t max_ent, int32_t max_acc) {
   const int32_t m = off[n];
   const int32_t rows = 1 << shift;
   const uint32_t mask = (uint32_t)rows - 1u;
   b.shift = shift;
   b.nbins = (int32_t)(((int64_t)n + rows - 1) >> shift);
   b.ranges.clear();
-  // 1. ranges of consecutive sources: at most kBinSrc sources and kBinEnt
-  // entries each; a source with more than kBinEnt entries is cut into ranges
+  // 1. ranges of consecutive sources: at most max_src sources and max_ent
+  // entries each; a source with more than max_ent entries is cut into ranges
   // of its own
   for (int32_t j = 0; j < n;) {
     const int32_t d = off[j + 1] - off[j];
-    if (d > kBinEnt) {
-      for (int32_t e = off[j]; e < off[j + 1]; e += kBinEnt)
-        b.ranges.push_back(BinRange{j, j + 1, e, std::min(e + kBinEnt, off[j + 1]), 0, 0});
+    if (d > max_ent) {
+      for (int32_t e = off[j]; e < off[j + 1]; e += max_ent)
+        b.ranges.push_back(BinRange{j, j + 1, e, std::min(e + max_ent, off[j + 1]), 0, 0});
       ++j;
       continue;
     }
     const int32_t j0 = j;
     int32_t ents = 0;
-    while (j < n && j - j0 < kBinSrc) {
+    while (j < n && j - j0 < max_src) {
       const int32_t dj = off[j + 1] - off[j];
-      if (dj > kBinEnt || ents + dj > kBinEnt) break;
+      if (dj > max_ent || ents + dj > max_ent) break;
       ents += dj;
       ++j;
     }
@@ -462,21 +463,21 @@ void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shi
       }
     }
   });
-  // 5. accumulate items: one per bin, or one per kBinAccEnt entries with a
+  // 5. accumulate items: one per bin, or one per max_acc entries with a
   // partial-sum slot each
   b.items.clear();
   b.splits.clear();
   b.nslots = 0;
   for (int32_t k = 0; k < b.nbins; ++k) {
     const int32_t p0 = b.bin_off[(size_t)k], p1 = b.bin_off[(size_t)k + 1];
-    if (p1 - p0 <= kBinAccEnt) {
+    if (p1 - p0 <= max_acc) {
       b.items.push_back(BinItem{k, p0, p1, -1});
       continue;
     }
-    const int32_t ns = (int32_t)(((int64_t)p1 - p0 + kBinAccEnt - 1) / kBinAccEnt);
+    const int32_t ns = (int32_t)(((int64_t)p1 - p0 + max_acc - 1) / max_acc);
     b.splits.push_back(BinSplit{k, b.nslots, ns});
     for (int32_t t = 0; t < ns; ++t)
-      b.items.push_back(BinItem{k, p0 + t * kBinAccEnt, std::min(p1, p0 + (t + 1) * kBinAccEnt), b.nslots + t});
+      b.items.push_back(BinItem{k, p0 + t * max_acc, std::min(p1, p0 + (t + 1) * max_acc), b.nslots + t});
     b.nslots += ns;
   }
 }

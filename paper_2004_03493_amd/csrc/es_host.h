@@ -81,18 +81,9 @@ bool pack_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, bo
 // is a sequential one; the per-edge traffic is a 2-byte source slot and a
 // 4-byte position, the 8-byte value written and read back, and a 2-byte row
 // slot.
-#ifndef ES_BIN_SRC
-#define ES_BIN_SRC 8192
-#endif
-#ifndef ES_BIN_ENT
-#define ES_BIN_ENT (1 << 18)
-#endif
-#ifndef ES_BIN_ACC_ENT
-#define ES_BIN_ACC_ENT (1 << 18)
-#endif
-constexpr int kBinSrc = ES_BIN_SRC;        // sources staged per scatter workgroup (64 KiB of values)
-constexpr int kBinEnt = ES_BIN_ENT;        // entries per scatter workgroup
-constexpr int kBinAccEnt = ES_BIN_ACC_ENT; // entries per accumulate workgroup (larger bins are split)
+constexpr int kBinSrc = 16384;       // sources staged per scatter workgroup (128 KiB of values)
+constexpr int kBinEnt = 1 << 20;     // entries per scatter workgroup
+constexpr int kBinAccEnt = 1 << 20;  // entries per accumulate workgroup (longer bins are split)
 
 struct BinRange {
   int32_t j0, j1;  // sources [j0, j1) (one source when its list is cut into several ranges)
@@ -131,8 +122,11 @@ struct BinnedLayout {
 };
 
 // Push lists: source j sends to idx[off[j] .. off[j+1]) (destination rows in
-// [0, n)); shift in [1, 16].
-void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b);
+// [0, n)); shift in [1, 16].  max_src / max_ent / max_acc (at most the
+// defaults) bound the sources and entries of a scatter range and the entries
+// of an accumulate item.
+void build_binned(const int32_t* off, const int32_t* idx, int32_t n, int32_t shift, BinnedLayout& b,
+                  int32_t max_src = kBinSrc, int32_t max_ent = kBinEnt, int32_t max_acc = kBinAccEnt);
 
 // Degree-ordered relabelling and the two CSR copies under internal ids.
 // keys: edges (src << 32 | dst) in external ids, sorted ascending, distinct

@@ -312,16 +312,10 @@ void free_plan(SpmvPlan* plan);
 es_status build_binned_plan(es_ctx* ctx, const int32_t* off, const int32_t* idx, int32_t n, int32_t shift,
                             size_t row_bytes, BinnedPlan* plan);
 void free_binned_plan(BinnedPlan* plan);
-// rows per bin of the two directions: 2^13 int64 sums (forward), 2^12
-// 128-bit sums (backward), 64 KiB of LDS each
-#ifndef ES_BIN_SHIFT_FWD
-#define ES_BIN_SHIFT_FWD 13
-#endif
-#ifndef ES_BIN_SHIFT_BACK
-#define ES_BIN_SHIFT_BACK 12
-#endif
-constexpr int32_t kBinShiftFwd = ES_BIN_SHIFT_FWD;
-constexpr int32_t kBinShiftBack = ES_BIN_SHIFT_BACK;
+// rows per bin of the two directions: 2^14 int64 sums (forward, 128 KiB of
+// LDS), 2^12 128-bit sums (backward, 64 KiB)
+constexpr int32_t kBinShiftFwd = 14;
+constexpr int32_t kBinShiftBack = 12;
 // graphs with at least this many nodes take the binned pass unless the
 // caller asks for the pull pass
 constexpr int32_t kBinnedAutoNodes = 1 << 24;

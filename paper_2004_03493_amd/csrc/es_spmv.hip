@@ -218,14 +218,8 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_pull_kernel(const BlockDesc
 // order.
 
 constexpr int kBinThreads = 1024;
-#ifndef ES_BIN_SCATTER_UNROLL
-#define ES_BIN_SCATTER_UNROLL 4
-#endif
-#ifndef ES_BIN_ACC_UNROLL
-#define ES_BIN_ACC_UNROLL 4
-#endif
+
 constexpr int kFixBits = 72;  // backward terms as multiples of 2^-72
-constexpr double kFixB = 0x1p72;
 constexpr double kFixBInv = 0x1p-72;
 
 template <class V>
@@ -238,7 +232,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const BinRange
   const int tid = threadIdx.x;
   for (int t = tid; t < r.j1 - r.j0; t += kBinThreads) xs[t] = x[r.j0 + t];
   __syncthreads();
-  constexpr int kU = ES_BIN_SCATTER_UNROLL;
+  constexpr int kU = 4;
   for (int k = r.e0 + tid; k < r.e1; k += kU * kBinThreads) {
     uint32_t sl[kU], ps[kU];
 #pragma unroll
@@ -265,7 +259,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_acc_fwd_kernel(const BinItem*
   const int tid = threadIdx.x;
   for (int t = tid; t < kRows; t += kBinThreads) acc[t] = 0ull;
   __syncthreads();
-  constexpr int kU = ES_BIN_ACC_UNROLL;
+  constexpr int kU = 4;
   for (int p = it.p0 + tid; p < it.p1; p += kU * kBinThreads) {
     uint32_t rr[kU];
     unsigned long long v[kU];
@@ -358,7 +352,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_acc_back_kernel(const BinItem
     ahi[t] = 0ull;
   }
   __syncthreads();
-  constexpr int kU = ES_BIN_ACC_UNROLL;
+  constexpr int kU = 4;
   for (int p = it.p0 + tid; p < it.p1; p += kU * kBinThreads) {
     uint32_t rr[kU];
     double v[kU];

@@ -97,9 +97,10 @@ static int check_tiles(const std::vector<int32_t>& off, int32_t n) {
 
 // Binned layout: every edge appears once as (source, destination row), every
 // value position once, ranges and items within their limits and in order.
-static int check_binned(const std::vector<int32_t>& off, const std::vector<int32_t>& idx, int32_t n, int32_t shift) {
+static int check_binned(const std::vector<int32_t>& off, const std::vector<int32_t>& idx, int32_t n, int32_t shift,
+                        int32_t max_src = kBinSrc, int32_t max_ent = kBinEnt, int32_t max_acc = kBinAccEnt) {
   BinnedLayout b;
-  build_binned(off.data(), idx.data(), n, shift, b);
+  build_binned(off.data(), idx.data(), n, shift, b, max_src, max_ent, max_acc);
   const int32_t m = off[n];
   CHECK(b.nbins == (int32_t)(((int64_t)n + (1 << shift) - 1) >> shift));
   CHECK((int32_t)b.bin_off.size() == b.nbins + 1 && b.bin_off[0] == 0 && b.bin_off[b.nbins] == m);
@@ -110,8 +111,8 @@ static int check_binned(const std::vector<int32_t>& off, const std::vector<int32
   std::vector<uint8_t> hit((size_t)m, 0);
   int32_t next_e = 0, next_j = 0;
   for (const BinRange& r : b.ranges) {
-    CHECK(r.e0 == next_e && r.e0 <= r.e1 && r.e1 - r.e0 <= kBinEnt);
-    CHECK(r.j0 < r.j1 && r.j1 - r.j0 <= kBinSrc && r.j1 <= n);
+    CHECK(r.e0 == next_e && r.e0 <= r.e1 && r.e1 - r.e0 <= max_ent);
+    CHECK(r.j0 < r.j1 && r.j1 - r.j0 <= max_src && r.j1 <= n);
     CHECK(r.j0 == next_j || (r.j0 == next_j - 1 && r.j1 == r.j0 + 1));  // cut lists repeat their source
     CHECK(r.e0 >= off[r.j0] && r.e1 <= off[r.j1]);
     next_e = r.e1;
@@ -154,7 +155,7 @@ static int check_binned(const std::vector<int32_t>& off, const std::vector<int32
     int32_t count = 0;
     while (it < (int32_t)b.items.size() && b.items[(size_t)it].bin == bin) {
       const BinItem& x = b.items[(size_t)it];
-      CHECK(x.p0 == p && x.p0 <= x.p1 && x.p1 - x.p0 <= kBinAccEnt);
+      CHECK(x.p0 == p && x.p0 <= x.p1 && x.p1 - x.p0 <= max_acc);
       p = x.p1;
       ++count;
       ++it;
@@ -216,8 +217,12 @@ static int run(const char* name, int32_t n, const std::vector<int32_t>& src, con
   CHECK(rebuilt == keys);
   if (check_partition(h.out_off, n) || check_partition(h.in_off, n)) return 1;
   if (check_tiles(h.out_off, n) || check_tiles(h.in_off, n)) return 1;
-  for (int32_t shift : {1, 4, 13})
+  for (int32_t shift : {1, 4, 12, 14})
     if (check_binned(h.in_off, h.in_idx, n, shift) || check_binned(h.out_off, h.out_idx, n, shift)) return 1;
+  // small limits: cut push lists, split bins, source-bound ranges
+  if (check_binned(h.in_off, h.in_idx, n, 12, 100, 5000, 3000) ||
+      check_binned(h.out_off, h.out_idx, n, 12, 100, 5000, 3000))
+    return 1;
   std::printf("%s: n=%d m=%lld ok\n", name, n, (long long)m);
   return 0;
 }
@@ -274,8 +279,8 @@ int main() {
   }
   {
     // a node with more in- and out-neighbours than a scatter range and an
-    // accumulate item take: cut push lists, split bins
-    const int32_t n = 300001;
+    // accumulate item take at the default limits: cut push lists, split bins
+    const int32_t n = 1100001;
     std::vector<int32_t> s, d;
     for (int32_t v = 1; v < n; ++v) {
       s.push_back(v);
@@ -283,7 +288,7 @@ int main() {
       s.push_back(0);
       d.push_back(v);
     }
-    rc |= run("star of 3e5 leaves both ways", n, s, d, true, true);
+    rc |= run("star of 1.1e6 leaves both ways", n, s, d, true, true);
   }
   {
     // an endpoint out of range is reported, not read past

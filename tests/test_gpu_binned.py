@@ -52,9 +52,9 @@ GRAPHS = {
     "random_5000": lambda: random_graph(5000, 40000, 3),
     "chung_lu_20001": lambda: (20001,) + workloads.chung_lu(20001, 200000, 12),
     "rmat_32k": lambda: (1 << 15,) + workloads.rmat(1 << 15, 500_000, 5),
-    # a node with 3e5 in-neighbours and one with 3e5 out-neighbours: push
+    # a node with 1.1e6 in-neighbours and one with 1.1e6 out-neighbours: push
     # lists cut over several scatter ranges, bins split over several items
-    "hubs_3e5": lambda: hub_graph(310_000, 300_000, 300_000, 200_000, 4),
+    "hubs_1e6": lambda: hub_graph(1_200_000, 1_100_000, 1_100_000, 400_000, 4),
 }
 
 _cache = {}
@@ -116,7 +116,7 @@ def test_binned_backward(es, ctx, name):
 
 
 @pytest.mark.parametrize("name,r_scale,sparse_eps", [("random_5000", 1e-4, 0.0), ("chung_lu_20001", 1e-4, 0.0),
-                                                     ("chung_lu_20001", 1e-4, 1e-3), ("hubs_3e5", 1e-6, 1e-4)])
+                                                     ("chung_lu_20001", 1e-4, 1e-3), ("hubs_1e6", 1e-6, 1e-4)])
 def test_binned_query(es, ctx, name, r_scale, sparse_eps):
     gb, gp, og = pair(es, ctx, name)
     u = int(np.argmax(og.din))
