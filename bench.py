@@ -371,8 +371,15 @@ def rmat42m_block(args, r_scale, steps, warmup, accuracy):
                 pairs[name] += st.pairs
         log(f"# accuracy u={u}: " + " ".join(f"{k} {v[-2:]}" for k, v in acc.items()))
     L = timed["pi2"][1][0].L
-    fwd_bytes = L * (4.0 * g.m + 28.0 * g.n)
-    back_bytes = L * (4.0 * g.m + 44.0 * g.n)
+    # algorithmic bytes of the level passes: the pull pass reads each index once and
+    # gathers the operand (4m + 28n forward, 4m + 44n backward); the binned pass writes
+    # and reads back one value per edge with its slots (24m + 32n, 24m + 40n)
+    if g.binned:
+        fwd_bytes = L * (24.0 * g.m + 32.0 * g.n)
+        back_bytes = L * (24.0 * g.m + 40.0 * g.n)
+    else:
+        fwd_bytes = L * (4.0 * g.m + 28.0 * g.n)
+        back_bytes = L * (4.0 * g.m + 44.0 * g.n)
 
     def summary(name):
         el, st = timed[name]
@@ -408,10 +415,15 @@ def rmat42m_block(args, r_scale, steps, warmup, accuracy):
         "pi2_lde_reduced_sparse": prs,
         "sparse_eps": eps,
         "roofline_spmv": {
-            "kernel": "spmv_pull_kernel (forward, 29 levels)", "bound": "hbm",
+            "kernel": (f"bin_scatter_kernel + bin_acc_fwd_kernel (binned level pass, forward, {L} levels)"
+                       if g.binned else f"spmv_pull_kernel (forward, {L} levels)"), "bound": "hbm",
             "achieved": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": fwd_bytes / (pp["ms_forward"] / 1e3) / 1e9 / PEAK_HBM_GBS,
             "backward_achieved": back_bytes / (pp["ms_backward"] / 1e3) / 1e9,
+            "algorithmic_bytes_per_level": fwd_bytes / L,
+            "ms_forward_level": pp["ms_forward"] / L, "ms_backward_level": pp["ms_backward"] / L,
+            # the pull pass's algorithmic bytes (4m + 28n) over the same time, for comparison
+            "pull_bytes_frac": L * (4.0 * g.m + 28.0 * g.n) / (pp["ms_forward"] / 1e3) / 1e9 / PEAK_HBM_GBS,
         },
         "accuracy": {
             "reference": f"pi^2 allocation, {args.ref_factor:g}x the budget, walk seed {wl.seed_walk + 1000}",
