@@ -381,62 +381,88 @@ __device__ __forceinline__ u128 weighted_square(uint64_t V, double inv_d) {
 // Read back the regions of origins [o0, o1): per origin at level `lev`
 //   N = sum d_in(q), SN = sum N_1(q), C = sum V^2 (2^-124), Cw = sum V^2/d_in(q) (2^-120)
 // over the distinct keys q, and the entries of origins that go deeper.
+// Regions are whole 64-slot pages (at least 64 slots, sizes powers of two),
+// so a wave's 64 lanes always share one region; each wave walks a contiguous
+// run of pages, keeps its sums in registers while the region stays the same
+// and adds them to the region's statistics when it leaves it, and appends
+// the entries that go deeper with one counter update per wave.
 __global__ void compact_kernel(int64_t S, const long long* __restrict__ reg_off, int32_t nreg, int32_t o0,
                                const int32_t* __restrict__ keys, const unsigned long long* __restrict__ vals,
                                const int32_t* __restrict__ din, const double* __restrict__ inv_din,
                                const long long* __restrict__ N1, const int32_t* __restrict__ depth, int32_t lev,
                                unsigned long long* __restrict__ stats, Ent* __restrict__ out,
                                unsigned long long* __restrict__ nout) {
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // whole waves iterate together so the shuffles see every lane
-  const int64_t iters = (S + nthreads - 1) / nthreads;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t s = first + it * nthreads;
-    int32_t r = -1;
-    int32_t q = -1;
-    if (s < S) {
-      int32_t lo = 0, hi = nreg - 1;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (reg_off[mid] <= s) lo = mid;
-        else hi = mid - 1;
-      }
-      r = lo;
-      q = keys[s];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t pages = S >> 6;
+  const int64_t per = (pages + nwaves - 1) / nwaves;
+  const int64_t p0 = wave * per;
+  const int64_t p1 = min(pages, p0 + per);
+  if (p0 >= p1) return;  // whole wave
+  // region of the first page: the last r with reg_off[r] <= slot
+  int32_t r = 0;
+  {
+    int32_t lo = 0, hi = nreg - 1;
+    const long long s0 = p0 << 6;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (reg_off[mid] <= s0) lo = mid;
+      else hi = mid - 1;
     }
-    unsigned long long nsum = 0, snsum = 0;
-    u128 csum = 0, wsum = 0;
-    if (q >= 0) {
-      const uint64_t V = vals[s];
-      nsum = (unsigned long long)din[q];
-      snsum = (unsigned long long)N1[q];
-      csum = (u128)V * (u128)V;
-      wsum = din[q] > 0 ? weighted_square(V, inv_din[q]) : (u128)0;
-      const int32_t o = o0 + r;
-      if (depth[o] > lev) {
-        const unsigned long long pos = atomicAdd(nout, 1ull);
-        out[pos] = Ent{o, q, V};
-      }
+    r = lo;
+  }
+  long long rend = reg_off[r + 1];
+  bool deeper = depth[o0 + r] > lev;
+  unsigned long long nsum = 0, snsum = 0;
+  u128 csum = 0, wsum = 0;
+  auto flush = [&]() {
+    for (int m = 32; m > 0; m >>= 1) {
+      nsum += __shfl_xor(nsum, m, 64);
+      snsum += __shfl_xor(snsum, m, 64);
+      csum += shfl_xor_u128(csum, m);
+      wsum += shfl_xor_u128(wsum, m);
     }
-    const int32_t r0 = __shfl(r, 0, 64);
-    const bool uniform = __all(r == r0) && r0 >= 0;
-    if (uniform) {
-      for (int m = 32; m > 0; m >>= 1) {
-        nsum += __shfl_xor(nsum, m, 64);
-        snsum += __shfl_xor(snsum, m, 64);
-        csum += shfl_xor_u128(csum, m);
-        wsum += shfl_xor_u128(wsum, m);
-      }
-    }
-    if ((uniform && (threadIdx.x & 63) == 0) || (!uniform && q >= 0)) {
+    if (lane == 0) {
       unsigned long long* st = stats + ((int64_t)(o0 + r) * (kMaxLevel + 1) + lev) * kStatWords;
       if (nsum) atomicAdd(&st[0], nsum);
       if (snsum) atomicAdd(&st[1], snsum);
       if (csum) atomic_add_u128(&st[2], csum);
       if (wsum) atomic_add_u128(&st[4], wsum);
     }
+    nsum = snsum = 0;
+    csum = wsum = 0;
+  };
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int64_t p = p0; p < p1; ++p) {
+    const long long s = (p << 6) + lane;
+    if ((p << 6) >= rend) {
+      flush();
+      do {
+        ++r;
+        rend = reg_off[r + 1];
+      } while ((p << 6) >= rend);
+      deeper = depth[o0 + r] > lev;
+    }
+    const int32_t q = keys[s];
+    uint64_t V = 0;
+    if (q >= 0) {
+      V = vals[s];
+      const int32_t d = din[q];
+      nsum += (unsigned long long)d;
+      snsum += (unsigned long long)N1[q];
+      csum += (u128)V * (u128)V;
+      if (d > 0) wsum += weighted_square(V, inv_din[q]);
+    }
+    const unsigned long long go = __ballot(deeper && q >= 0);
+    if (go) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(nout, (unsigned long long)__popcll(go));
+      base = __shfl(base, 0, 64);
+      if ((go >> lane) & 1ull) out[base + __popcll(go & below)] = Ent{o0 + r, q, V};
+    }
   }
+  flush();
 }
 
 __global__ void zero_u64_kernel(int64_t n, unsigned long long* __restrict__ p) {
@@ -570,7 +596,7 @@ es_status propagate(es_ctx* ctx, const es_graph* g, const std::vector<int32_t>& 
     for (int32_t i = 0; i < no; ++i) {
       if (depth[i] <= j || ins[i] == 0) continue;
       const int64_t distinct = (int64_t)std::min<uint64_t>(ins[i], (uint64_t)n);
-      cap[i] = pow2_at_least(2 * distinct);
+      cap[i] = std::max<int64_t>(64, pow2_at_least(2 * distinct));  // whole 64-slot pages
       if (depth[i] > j + 1) next_cap += distinct;
     }
     const int nxt_slot = cur_slot == kWsLdeEnt0 ? kWsLdeEnt1 : kWsLdeEnt0;
