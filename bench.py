@@ -54,8 +54,11 @@ OPS_PER_PHILOX_BLOCK = 10 * (2 * (4 + 2) + 8)
 # one joint walk step: two 64x32 multiply-high index maps (6 ops each)
 OPS_PER_WALK_STEP = 12
 
-WALK_SOURCE = os.path.join(ROOT, "paper_2004_03493_amd", "csrc", "es_walk.hip")
-SPMV_SOURCE = os.path.join(ROOT, "paper_2004_03493_amd", "csrc", "es_spmv.hip")
+CSRC = os.path.join(ROOT, "paper_2004_03493_amd", "csrc")
+# sources that define a kernel's code and data layout: committed counters count only while
+# they hash the same
+WALK_SOURCE = [os.path.join(CSRC, f) for f in ("es_walk.hip", "es_internal.h", "es_core.hip")]
+SPMV_SOURCE = [os.path.join(CSRC, f) for f in ("es_spmv.hip", "es_internal.h", "es_host.h", "es_host.cpp")]
 COUNTERS = os.path.join(ROOT, "profiles", "walk_pairs_kernel_rmat_n1048576_counters.md")
 
 
@@ -96,9 +99,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():

@@ -20,7 +20,10 @@ __global__ void walk_adj_kernel(int64_t m, const int32_t* __restrict__ in_off, c
     const int32_t v = in_idx[e];
     const int32_t o = in_off[v];
     const int32_t d = in_off[v + 1] - o;
-    adj[e] = WalkEntry{d > 0 ? o : -1 - v, d, 0, 0};
+    WalkEntry w{};
+    w.key = d > 0 ? o : -1 - v;
+    w.deg = d;
+    adj[e] = w;
   }
 }
 
