@@ -32,18 +32,21 @@ def test_traffic_fields_follow_the_kernel_sources(tmp_path, monkeypatch):
     b = _bench_module()
     walk = tmp_path / "walk.hip"
     spmv = tmp_path / "spmv.hip"
+    layout = tmp_path / "layout.h"  # shared by both kernels
     walk.write_text("// walk kernel v1\n")
     spmv.write_text("// spmv kernel v1\n")
+    layout.write_text("// records v1\n")
+    walk_src, spmv_src = [str(walk), str(layout)], [str(spmv), str(layout)]
     counters = tmp_path / "counters.md"
     counters.write_text(
         "| kernel | dispatches | FETCH | WRITE | calibrated bytes / launch | hit |\n"
         "| void spmv_pull_kernel<long, FwdGather, FwdEpi> | 87 | 1.0 | 2.0 | 1.5e+08 | 0.9 |\n\n"
-        f"    kernel_source_sha256_16: {b.source_hash(str(walk))}\n"
+        f"    kernel_source_sha256_16: {b.source_hash(walk_src)}\n"
         "    hbm_bytes_per_launch: 1.25e+12\n"
-        f"    spmv_source_sha256_16: {b.source_hash(str(spmv))}\n")
+        f"    spmv_source_sha256_16: {b.source_hash(spmv_src)}\n")
     monkeypatch.setattr(b, "COUNTERS", str(counters))
-    monkeypatch.setattr(b, "WALK_SOURCE", str(walk))
-    monkeypatch.setattr(b, "SPMV_SOURCE", str(spmv))
+    monkeypatch.setattr(b, "WALK_SOURCE", walk_src)
+    monkeypatch.setattr(b, "SPMV_SOURCE", spmv_src)
     assert b.measured_traffic() == 1.25e12
     assert b.measured_spmv_traffic() == 1.5e8
     walk.write_text("// walk kernel v2\n")
@@ -51,6 +54,12 @@ def test_traffic_fields_follow_the_kernel_sources(tmp_path, monkeypatch):
     assert b.measured_spmv_traffic() == 1.5e8
     spmv.write_text("// spmv kernel v2\n")
     assert b.measured_spmv_traffic() is None
+    # a change to a layout header both kernels include voids both figures
+    walk.write_text("// walk kernel v1\n")
+    spmv.write_text("// spmv kernel v1\n")
+    assert b.measured_traffic() == 1.25e12 and b.measured_spmv_traffic() == 1.5e8
+    layout.write_text("// records v2\n")
+    assert b.measured_traffic() is None and b.measured_spmv_traffic() is None
     monkeypatch.setattr(b, "COUNTERS", str(tmp_path / "missing.md"))
     assert b.measured_traffic() is None and b.measured_spmv_traffic() is None
 
