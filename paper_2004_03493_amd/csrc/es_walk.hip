@@ -249,34 +249,28 @@ __global__ void zero_totals_kernel(WalkTotals* tot) {
 
 // ---- Philox4x64-10 (Salmon et al., SC 2011) --------------------------------
 
-// 64 x 64 -> 128-bit product.  kShared: from four 32 x 32 -> 64 multiply-adds
-// that share their partial products (no separate low product; each sum fits
-// in 64 bits):
+// 64 x 64 -> 128-bit product from four 32 x 32 -> 64 multiply-adds that
+// share their partial products (no separate low product; each sum fits in
+// 64 bits):
 //   t = a1 b0 + hi(a0 b0),  w = a0 b1 + lo(t),
 //   hi = a1 b1 + hi(t) + hi(w),  lo = lo(w) 2^32 + lo(a0 b0).
-// Fewer instructions, but longer-lived temporaries: it pays only in the
-// instantiation whose loop keeps its registers without spilling.
-template <bool kShared>
+// Fewer instructions than a low product plus a high product; its longer-lived
+// temporaries cost the batched and non-stop instantiations a few spilled
+// registers, and they still run 1-3% faster with it.
 __device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
-  if constexpr (kShared) {
-    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    const uint64_t p00 = (uint64_t)a0 * b0;
-    const uint64_t t = (uint64_t)a1 * b0 + (p00 >> 32);
-    const uint64_t w = (uint64_t)a0 * b1 + (uint32_t)t;
-    hi = (uint64_t)a1 * b1 + ((t >> 32) + (w >> 32));
-    lo = (w << 32) | (uint32_t)p00;
-  } else {
-    lo = a * b;
-    hi = __umul64hi(a, b);
-  }
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a1 * b0 + (p00 >> 32);
+  const uint64_t w = (uint64_t)a0 * b1 + (uint32_t)t;
+  hi = (uint64_t)a1 * b1 + ((t >> 32) + (w >> 32));
+  lo = (w << 32) | (uint32_t)p00;
 }
 
 struct Words {
   uint64_t w0, w1, w2, w3;
 };
 
-template <bool kShared>
 __device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                                uint64_t k1) {
   constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -288,8 +282,8 @@ __device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_
       k1 += W1;
     }
     uint64_t hi0, lo0, hi1, lo1;
-    mulhilo64<kShared>(M0, c0, hi0, lo0);
-    mulhilo64<kShared>(M1, c2, hi1, lo1);
+    mulhilo64(M0, c0, hi0, lo0);
+    mulhilo64(M1, c2, hi1, lo1);
     const uint64_t n0 = hi1 ^ c1 ^ k0;
     const uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -493,7 +487,7 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
       const uint64_t c1 = need_life ? (r >> 2) : r;
       const uint64_t c2 = need_life ? 0ull : (uint64_t)(t >> 1);
       const uint64_t c3 = need_life ? 1ull : 0ull;
-      const Words w = philox4x64_10<!kBuckets && !kNonstop>((uint64_t)pkc, c1, c2, c3, a.seed, 0ull);
+      const Words w = philox4x64_10((uint64_t)pkc, c1, c2, c3, a.seed, 0ull);
       ++nblocks;
       if (need_life) {
         lk = pk;
