@@ -275,6 +275,11 @@ __device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_
                                                uint64_t k1) {
   constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  // an empty asm that "changes" k0 keeps the compiler from hoisting the ten
+  // round keys out of the walk loop into scalar registers, which it then
+  // spilled to vector-register lanes and read back with v_readlane in every
+  // round; recomputing them with scalar adds is free
+  asm volatile("" : "+s"(k0));
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     if (round > 0) {
