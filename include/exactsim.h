@@ -84,9 +84,11 @@ typedef enum {
 #define ES_LEVELS_PULL 4u      /* each row gathers its terms (two int32 CSRs only)          */
 #define ES_LEVELS_BINNED 8u    /* push form in bins of destination rows: the sources are
                                   streamed, one 8-byte value per edge is written to its
-                                  bin and summed there in LDS; costs 8 + 2 x 4 bytes per
-                                  edge of device memory more and is the faster pass once
-                                  the level vectors no longer fit in the caches          */
+                                  bin and summed there in LDS; costs 24 bytes per edge of
+                                  device memory more (per direction a 2-byte source slot,
+                                  a 4-byte position and a 2-byte row slot; the values)
+                                  and is the faster pass once the level vectors no
+                                  longer fit in the caches                               */
 
 typedef struct {
   double c;                  /* decay factor, 0 < c <= 0.99 (the paper uses 0.6)            */
