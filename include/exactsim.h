@@ -417,13 +417,16 @@ typedef struct {
  * With opts->sparse_eps > 0 every source keeps only its level entries above
  * (1-sqrt c)^2 sparse_eps, as its single-source query does, in one list for
  * the whole batch (the dense level of the moment stays in one slot).
+ * With opts->alloc = ES_ALLOC_LEARNED every source takes its own weighted
+ * allocation (the floor and the normalisation from that source's pi, as in
+ * es_budget_weighted) over the graph's cached predictions.
  * stats (nullable): pairs = pairs simulated, pairs_requested = sum over queries,
  * meets = sum over queries of sum_k M(k), level_entries / level_bytes over the
  * batch; times are 0 except ms_walk (all walks).
  * Errors: as es_single_source; ES_EINVAL for a bad graph index, source,
- * width or block width; ES_EUNSUPPORTED for d_override, the learned allocation, Algorithm 3
- * (lde != 0), or sparse levels when a batch holds 2^31 or more
- * (node, source) entries. */
+ * width or block width, the learned allocation without a loaded network;
+ * ES_EUNSUPPORTED for d_override, Algorithm 3 (lde != 0), or sparse levels
+ * when a batch holds 2^31 or more (node, source) entries. */
 es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, const int32_t* graph_of_query,
                    const int32_t* sources, int32_t nq, const es_query_opts* opts, const es_batch_opts* bopts,
                    double* const* s_out, es_stats* stats);

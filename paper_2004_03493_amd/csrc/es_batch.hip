@@ -38,6 +38,7 @@ struct BEntry {
   const double* inv_din;
   const int32_t* din;
   const int32_t* int_of;
+  const float* vhat;  // learned allocation: predicted variances by internal id (else unused)
   int32_t n;
   int32_t B;
   int32_t W;
@@ -233,6 +234,89 @@ __global__ void bat_budget(const BEntry* __restrict__ ents, const double* __rest
   Rk[E.base + i] = c;
 }
 
+// Learned allocation per source of a block, the single-source rule in the
+// block layout: pass 0 adds Q(pi^2 v) and Q(pi^2) over the source's nodes,
+// pass 1 Q(pi^2 max(v, thr)) and Q(pi^2) (Q(x) = round(x 2^62), exact
+// integer sums); each thread keeps one source's sums, then LDS, then one
+// global add per workgroup and source.
+__global__ __launch_bounds__(256) void bat_learned_sums(const BEntry* __restrict__ ents, const double* __restrict__ pi,
+                                                        const double* __restrict__ thr, int32_t exact_small_din,
+                                                        int32_t pass, unsigned long long* __restrict__ S) {
+  __shared__ unsigned long long sa[kBatchMaxB], sb[kBatchMaxB];
+  const BEntry E = ents[blockIdx.y];
+  const int tid = threadIdx.x;
+  if (tid < kBatchMaxB) {
+    sa[tid] = 0ull;
+    sb[tid] = 0ull;
+  }
+  __syncthreads();
+  const int rows = blockDim.x / E.B;  // nodes per workgroup step
+  const int b = tid % E.B;
+  const int rl = tid / E.B;
+  unsigned long long a = 0, c = 0;
+  if (rl < rows) {
+    const double t = pass ? thr[E.src_base + b] : 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * rows + rl; r < E.n; r += (int64_t)gridDim.x * rows) {
+      const double p = pi[E.base + r * E.B + b];
+      if (p > 0.0 && (!exact_small_din || E.din[r] >= 2)) {
+        const double p2 = p * p;
+        double w = (double)E.vhat[r];
+        if (pass && t > w) w = t;
+        a += (unsigned long long)(int64_t)rint((p2 * w) * 0x1p62);
+        c += (unsigned long long)(int64_t)rint(p2 * 0x1p62);
+      }
+    }
+    atomicAdd(&sa[b], a);
+    atomicAdd(&sb[b], c);
+  }
+  __syncthreads();
+  if (tid < E.B) {
+    unsigned long long* d = S + (E.src_base + tid) * 4 + 2 * pass;
+    if (sa[tid]) atomicAdd(&d[0], sa[tid]);
+    if (sb[tid]) atomicAdd(&d[1], sb[tid]);
+  }
+}
+
+// Per source: the floor thr = f * vbar after pass 0, vbar_inv = S3 / S2 after
+// pass 1 (-1: no weighted mass, the plain pi^2 rule).
+__global__ void bat_learned_scalars(int32_t nq, const unsigned long long* __restrict__ S, double floor_ratio,
+                                    int32_t pass, double* __restrict__ thr, double* __restrict__ vbar_inv) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const unsigned long long* s = S + (int64_t)q * 4;
+  if (pass == 0) {
+    const int64_t s1 = (int64_t)s[0], s2 = (int64_t)s[1];
+    thr[q] = s1 > 0 ? floor_ratio * ((double)s1 / (double)s2) : 0.0;
+  } else {
+    const int64_t s1 = (int64_t)s[2], s2 = (int64_t)s[3];
+    vbar_inv[q] = s1 > 0 ? (double)s2 / (double)s1 : -1.0;
+  }
+}
+
+__global__ void bat_budget_learned(const BEntry* __restrict__ ents, const double* __restrict__ pi,
+                                   int32_t exact_small_din, const double* __restrict__ thr,
+                                   const double* __restrict__ vbar_inv, uint64_t* __restrict__ Rk) {
+  const BEntry E = ents[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (int64_t)E.n * E.B;
+  if (i >= nb) return;
+  const int32_t r = (int32_t)(i / E.B);
+  const int32_t b = (int32_t)(i - (int64_t)r * E.B);
+  const double p = pi[E.base + i];
+  const double vi = vbar_inv[E.src_base + b];
+  double want = E.R * (p * p);
+  if (vi >= 0.0) {
+    double w = (double)E.vhat[r];
+    const double t = thr[E.src_base + b];
+    if (t > w) w = t;
+    want = want * (w * vi);
+  }
+  uint64_t c = (uint64_t)ceil(want);
+  if (!(p > 0.0)) c = 0;
+  if (exact_small_din && E.din[r] <= 1) c = 0;
+  Rk[E.base + i] = c;
+}
+
 // One wave per node: sort the block's B counts ascending into T, Rmax = largest.
 __global__ void bat_sort_counts(const BEntry* __restrict__ ents, const uint64_t* __restrict__ Rk,
                                 uint64_t* __restrict__ T, uint64_t* __restrict__ Rmax) {
@@ -376,6 +460,8 @@ struct BatchPlan {
   int32_t alloc = 0, small = 0;
   int32_t nq = 0;
   double sparse_eps = 0;
+  double v_floor = 0;   // learned allocation: floor ratio and the network's load id
+  uint64_t mlp_id = 0;
   // device data
   BEntry* ents = nullptr;
   int32_t nent = 0;
@@ -387,6 +473,9 @@ struct BatchPlan {
   int32_t nlf = 0, nlb = 0;
   int32_t* src_int = nullptr;    // [nq] internal source ids, block order
   double** outs = nullptr;       // [nq] device pointer array, block order
+  unsigned long long* lsums = nullptr;  // learned allocation: [nq][4] sums, thresholds, vbar_inv
+  double* lthr = nullptr;
+  double* lvbi = nullptr;
   int64_t NB = 0, NN = 0, NLONG = 0;
   int32_t max_nb_blocks = 0;     // grid.x for per-block elementwise kernels
   int32_t max_n = 0;
@@ -408,6 +497,9 @@ void free_batch_plans(es_ctx* ctx) {
     (void)hipFree(p->long_back);
     (void)hipFree(p->src_int);
     (void)hipFree(p->outs);
+    (void)hipFree(p->lsums);
+    (void)hipFree(p->lthr);
+    (void)hipFree(p->lvbi);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     delete p;
     p = nx;
@@ -540,7 +632,18 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
     if (sparse) ES_TRY(launch_level_keep(ctx, NB, slot(l), false, b.pi, b.sp, l, p.L));
   }
   if (!sparse) bat_sum_levels<<<ceil_div(NB, tb), tb, 0, stream>>>(NB, p.L, b.levels, b.pi);
-  bat_budget<<<egrid, tb, 0, stream>>>(p.ents, b.pi, p.alloc, p.small, b.Rk);
+  if (p.alloc == ES_ALLOC_LEARNED) {
+    const int lgrid = std::min(p.max_nb_blocks, std::max(1, ctx->num_cus) * 4);
+    dim3 lg(lgrid, p.nent);
+    zero_u64<<<ceil_div((int64_t)p.nq * 4, tb), tb, 0, stream>>>((int64_t)p.nq * 4, p.lsums);
+    bat_learned_sums<<<lg, tb, 0, stream>>>(p.ents, b.pi, p.lthr, p.small, 0, p.lsums);
+    bat_learned_scalars<<<ceil_div(p.nq, tb), tb, 0, stream>>>(p.nq, p.lsums, p.v_floor, 0, p.lthr, p.lvbi);
+    bat_learned_sums<<<lg, tb, 0, stream>>>(p.ents, b.pi, p.lthr, p.small, 1, p.lsums);
+    bat_learned_scalars<<<ceil_div(p.nq, tb), tb, 0, stream>>>(p.nq, p.lsums, p.v_floor, 1, p.lthr, p.lvbi);
+    bat_budget_learned<<<egrid, tb, 0, stream>>>(p.ents, b.pi, p.small, p.lthr, p.lvbi, b.Rk);
+  } else {
+    bat_budget<<<egrid, tb, 0, stream>>>(p.ents, b.pi, p.alloc, p.small, b.Rk);
+  }
   dim3 sgrid(ceil_div(p.max_n, tb / 64), p.nent);
   bat_sort_counts<<<sgrid, tb, 0, stream>>>(p.ents, b.Rk, b.T, b.Rmax);
   for (int32_t e = 0; e < p.nent; ++e) {
@@ -577,7 +680,7 @@ es_status enqueue_batch(es_ctx* ctx, const BatchPlan& p, const BatchBuffers& b,
 bool same_key(const BatchPlan& p, const BatchPlan& q) {
   return p.kid == q.kid && p.kg == q.kg && p.kB == q.kB && p.kW == q.kW && p.kG == q.kG && p.L == q.L && p.c == q.c &&
          p.eps == q.eps && p.r_scale == q.r_scale && p.seed == q.seed && p.alloc == q.alloc && p.small == q.small &&
-         p.nq == q.nq && p.sparse_eps == q.sparse_eps;
+         p.nq == q.nq && p.sparse_eps == q.sparse_eps && p.v_floor == q.v_floor && p.mlp_id == q.mlp_id;
 }
 
 // Build tiles and descriptors of a plan whose key fields are set.
@@ -601,6 +704,7 @@ es_status build_batch_plan(es_ctx* ctx, BatchPlan& p, const std::vector<BatchBlo
     E.inv_din = g->inv_din;
     E.din = g->din_int;
     E.int_of = g->int_of;
+    E.vhat = g->vhat;
     E.n = g->n;
     E.B = bl.B;
     E.W = bl.W;
@@ -651,6 +755,11 @@ es_status build_batch_plan(es_ctx* ctx, BatchPlan& p, const std::vector<BatchBlo
   ES_TRY(upload(ctx, &p.long_back, lbk));
   ES_CHECK_HIP(ctx, hipMalloc((void**)&p.src_int, sizeof(int32_t) * std::max(1, p.nq)));
   ES_CHECK_HIP(ctx, hipMalloc((void**)&p.outs, sizeof(double*) * std::max(1, p.nq)));
+  if (p.alloc == ES_ALLOC_LEARNED) {
+    ES_CHECK_HIP(ctx, hipMalloc((void**)&p.lsums, sizeof(unsigned long long) * 4 * std::max(1, p.nq)));
+    ES_CHECK_HIP(ctx, hipMalloc((void**)&p.lthr, sizeof(double) * std::max(1, p.nq)));
+    ES_CHECK_HIP(ctx, hipMalloc((void**)&p.lvbi, sizeof(double) * std::max(1, p.nq)));
+  }
   return ES_OK;
 }
 
@@ -799,8 +908,13 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ctx, ES_EINVAL, "eps=%g outside (0, 1)", o->eps);
   if (!(o->r_scale > 0.0)) return fail(ctx, ES_EINVAL, "r_scale=%g must be positive", o->r_scale);
   if (o->d_override) return fail(ctx, ES_EUNSUPPORTED, "d_override is single-source only");
-  if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI)
-    return fail(ctx, o->alloc == ES_ALLOC_LEARNED ? ES_EUNSUPPORTED : ES_EINVAL, "allocation %d", o->alloc);
+  if (o->alloc != ES_ALLOC_PI2 && o->alloc != ES_ALLOC_PI && o->alloc != ES_ALLOC_LEARNED)
+    return fail(ctx, ES_EINVAL, "allocation %d", o->alloc);
+  if (o->alloc == ES_ALLOC_LEARNED) {
+    if (!ctx->mlp_w) return fail(ctx, ES_EINVAL, "learned allocation without a loaded network (es_mlp_load)");
+    if (!(o->v_floor_ratio >= 0.0 && o->v_floor_ratio <= 1.0))
+      return fail(ctx, ES_EINVAL, "v_floor_ratio=%g outside [0, 1]", o->v_floor_ratio);
+  }
   if (o->lde != 0) return fail(ctx, ES_EUNSUPPORTED, "batches run Algorithm 2 only (lde = 0)");
   if (!(o->sparse_eps >= 0.0 && o->sparse_eps < 1.0))
     return fail(ctx, ES_EINVAL, "sparse_eps=%g outside [0, 1)", o->sparse_eps);
@@ -881,6 +995,12 @@ es_status es_batch(es_ctx* ctx, const es_graph* const* graphs, int32_t ngraphs, 
   key.small = o->exact_small_din;
   key.nq = nq;
   key.sparse_eps = o->sparse_eps;
+  if (o->alloc == ES_ALLOC_LEARNED) {
+    // predictions first: the plan's descriptors point at them
+    for (const auto& bl : blocks) ES_TRY(ensure_vhat(ctx, bl.g, o->c));
+    key.v_floor = o->v_floor_ratio;
+    key.mlp_id = ctx->mlp_id;
+  }
   BatchPlan* plan = nullptr;
   for (BatchPlan* p = ctx->plans; p; p = p->next)
     if (same_key(*p, key)) plan = p;

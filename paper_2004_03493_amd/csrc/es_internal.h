@@ -274,6 +274,9 @@ es_status launch_walks(es_ctx* ctx, const es_graph* g, const uint64_t* r_begin, 
 es_status launch_walks_buckets(es_ctx* ctx, const es_graph* g, const uint64_t* Rmax, const uint64_t* T, int32_t B,
                                uint64_t seed, double c, uint64_t* H, WalkTotals** totals_out);
 // Learned allocation (internal order): features, network, weighted budget.
+// ensure_vhat computes the graph's predicted variances for the loaded
+// network and decay c unless they are cached (stream-ordered; not capturable).
+es_status ensure_vhat(es_ctx* ctx, const es_graph* g, double c);
 es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
                                 int32_t exact_small_din, double floor_ratio, uint64_t* Rk);
 es_status launch_diag(es_ctx* ctx, const es_graph* g, const uint64_t* Rk, const uint64_t* M, const int32_t* din,

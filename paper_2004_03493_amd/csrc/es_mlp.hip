@@ -393,8 +393,7 @@ static es_status launch_weighted(es_ctx* ctx, int32_t n, const double* pi, const
 
 // Learned budget inside a query (internal node order): predicted variances
 // (cached in the graph per network and decay), then the weighted allocation.
-es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
-                                int32_t exact_small_din, double floor_ratio, uint64_t* Rk) {
+es_status ensure_vhat(es_ctx* ctx, const es_graph* g, double c) {
   const int32_t n = g->n;
   es_status st;
   if (!g->vhat || g->vhat_net != ctx->mlp_id || g->vhat_c != c) {
@@ -410,7 +409,13 @@ es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi
     g->vhat_net = ctx->mlp_id;
     g->vhat_c = c;
   }
-  return launch_weighted(ctx, n, pi, g->vhat, g->din_int, R, exact_small_din, floor_ratio, Rk);
+  return ES_OK;
+}
+
+es_status launch_learned_budget(es_ctx* ctx, const es_graph* g, const double* pi, double R, double c,
+                                int32_t exact_small_din, double floor_ratio, uint64_t* Rk) {
+  ES_TRY(ensure_vhat(ctx, g, c));
+  return launch_weighted(ctx, g->n, pi, g->vhat, g->din_int, R, exact_small_din, floor_ratio, Rk);
 }
 
 }  // namespace es

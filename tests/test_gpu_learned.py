@@ -308,3 +308,52 @@ def test_learned_predictions_cached_per_network(es, ctx, trained, cl2k):
     es.es_budget_weighted(ctx, g, pi, v, ox.total_samples(g.n, 0.8, eps, 1e-3), True, es.ES_LEARNED_FLOOR, Rk)
     st = run(0.8, s2)
     assert st.pairs == int(Rk.sum())
+
+
+def test_batch_learned_allocation_equals_single_source(es, ctx, trained, cl2k, rmat32k):
+    """The learned allocation in a batch: every source takes its own weighted
+    budget (floor and normalisation from its own pi), so each answer, its
+    requested pairs and its meetings equal its single-source learned query;
+    two graphs in one batch (a 37-source block of R-MAT 2^15 and 10 sources
+    of Chung-Lu 2,000), eager and replayed from a captured hipGraph."""
+    w, _, _ = trained
+    es.es_mlp_load(ctx, w)
+    gl = [cl2k[0], rmat32k[0]]
+    goq = [0] * 10 + [1] * 37
+    srcs = list(range(0, 100, 10)) + [int(x) for x in workloads.pick_sources(rmat32k[1].n, rmat32k[1].dst, 37, 8)]
+    opts = es.make_opts(C, 1e-4, 77, 1e-3, alloc=es.ES_ALLOC_LEARNED)
+    outs = [torch.full((gl[gi].n,), float("nan"), dtype=torch.float64, device="cuda") for gi in goq]
+    st = es.es_batch(ctx, gl, goq, srcs, opts, outs)
+    eager = [o.cpu().numpy() for o in outs]
+    meets = pairs = 0
+    s = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in gl]
+    for gi, u, got in zip(goq, srcs, eager):
+        st1 = es.es_single_source(ctx, gl[gi], u, opts, s[gi])
+        meets += st1.meets
+        pairs += st1.pairs
+        assert np.abs(got - s[gi].cpu().numpy()).max() <= 1e-13
+    assert st.pairs_requested == pairs and st.meets == meets
+    say(f"  {len(srcs)} learned queries in one batch: {pairs} pairs requested, {st.pairs} simulated")
+    outs2 = [torch.full((gl[gi].n,), float("nan"), dtype=torch.float64, device="cuda") for gi in goq]
+    for rep in range(2):
+        st2 = es.es_batch(ctx, gl, goq, srcs, opts, outs2, use_hip_graph=True)
+        assert st2.meets == meets
+        for a, b in zip(eager, outs2):
+            assert np.array_equal(a, b.cpu().numpy())
+    # the pi^2 rule in the same batch differs: the allocation is really applied
+    st3 = es.es_batch(ctx, gl, goq, srcs, es.make_opts(C, 1e-4, 77, 1e-3), outs2)
+    assert st3.pairs_requested != pairs
+
+
+def test_batch_learned_needs_a_network(es, ctx, cl2k):
+    """A fresh context has no network: the learned allocation is refused."""
+    c2 = es.Context(0)
+    try:
+        g = es.Graph(c2, 50, *[np.asarray(x) for x in workloads.chung_lu(50, 300, 3)])
+        out = [torch.empty(50, dtype=torch.float64, device="cuda")]
+        with pytest.raises(es.EsError) as e:
+            es.es_batch(c2, [g], [0], [0], es.make_opts(C, 1e-3, 1, 1e-3, alloc=es.ES_ALLOC_LEARNED), out)
+        assert e.value.status == es.ES_EINVAL
+        g.close()
+    finally:
+        c2.close()
