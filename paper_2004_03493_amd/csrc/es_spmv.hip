@@ -1,4 +1,5 @@
-// Level SpMV kernels of a single-source query (pull form over a CSR).
+// Level passes of a single-source query: the pull-form SpMV over a CSR and,
+// for graphs beyond the caches, the binned push form further below.
 //
 // Forward (Algorithm 1, l-hop PPR):  pi^l(i) = sqrt(c) * sum_{j in O(v_i)} pi^(l-1)(j)/d_in(j),
 //   each term pre-rounded to a multiple of 2^-62 and summed exactly in int64, so the
@@ -6,8 +7,8 @@
 // Backward (Algorithm 1, back-accumulation): s^l(j) = sqrt(c) (1/d_in(j)) sum_{i in I(v_j)} s^(l-1)(i)
 //   + D(j) pi^(L-l)(j)/(1-sqrt c), float64.
 //
-// Both are bound by HBM/Infinity-Cache traffic: the CSR index stream is read once
-// per level and the gathered operand (8 bytes per entry) comes through the caches.
+// Pull form: the CSR index stream is read once per level and the gathered
+// operand (8 bytes per entry) comes through the caches, one request per gather.
 // One workgroup of kSpmvThreads (512) lanes per row block: the block's column ids are streamed
 // coalesced, the gathered operands staged in LDS, then each row is reduced by a
 // group of lanes sized to the block's average row length.
