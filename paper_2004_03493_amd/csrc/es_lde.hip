@@ -34,7 +34,8 @@
 // C_1(a).  One kernel settles rounds 0 and 1 of every sampled node (most
 // nodes stop there) and lists the rest.  For those, the transition tables
 // (P^T)^j(x, .) of every needed origin x are built level by level in one
-// hash table whose regions belong to the origins: a load-balanced launch
+// hash table whose regions belong to the origins (a region that would need
+// n slots or more is a dense array indexed by node): a load-balanced launch
 // inserts every (origin, in-neighbour) term, values in 2^-62 fixed point
 // (each term rounded once, exact integer sums), keys inserted even for zero
 // terms so the supports are exact; a second launch reads each region back
@@ -304,12 +305,16 @@ __device__ __forceinline__ int64_t find_entry(const long long* __restrict__ pre,
 
 // Every (entry, in-neighbour) term once: the entry's value divided by d_in(x)
 // (rounded to nearest, ties up) added at key q of the origin's region.  A
-// block takes kInsertThreads * kInsertPer consecutive terms, interleaved over
-// its lanes so that neighbouring lanes read neighbouring in_idx entries.
+// block takes kInsertThreads * kInsertPer consecutive terms and each wave a
+// contiguous quarter of them, interleaved over its lanes so that neighbouring
+// lanes read neighbouring in_idx entries.  A lane's entry index only grows,
+// so the next one is found by galloping forward from the current one.  A
+// region of at least n slots is dense: key q sits in slot q (no probing, the
+// key written by plain stores of the same value).
 __global__ __launch_bounds__(kInsertThreads) void insert_kernel(
     long long total, int64_t ne, const Ent* __restrict__ ents, const long long* __restrict__ pre,
     const int32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx, const int32_t* __restrict__ din,
-    const long long* __restrict__ reg_off, int32_t o0, int32_t* __restrict__ keys,
+    const long long* __restrict__ reg_off, int32_t o0, int32_t n, int32_t* __restrict__ keys,
     unsigned long long* __restrict__ vals) {
   const long long b0 = (long long)blockIdx.x * kInsertThreads * kInsertPer;
   if (b0 >= total) return;
@@ -320,13 +325,32 @@ __global__ __launch_bounds__(kInsertThreads) void insert_kernel(
     range[1] = find_entry(pre, range[0], ne - 1, b1 - 1);
   }
   __syncthreads();
+  const int64_t r0 = range[0], r1 = range[1];
+  const long long w0 = b0 + (long long)(threadIdx.x >> 6) * 64 * kInsertPer;
+  const long long w1 = min(b1, w0 + 64ll * kInsertPer);
   int64_t last = -1;
   Ent en{};
   unsigned long long term = 0;
   long long base = 0, row = 0, first = 0;
   uint32_t mask = 0;
-  for (long long t = b0 + threadIdx.x; t < b1; t += kInsertThreads) {
-    const int64_t e = (last >= 0 && t < pre[last + 1]) ? last : find_entry(pre, range[0], range[1], t);
+  bool dense = false;
+  for (long long t = w0 + (threadIdx.x & 63); t < w1; t += 64) {
+    int64_t e = last;
+    if (last < 0) {
+      e = find_entry(pre, r0, r1, t);
+    } else if (t >= pre[last + 1]) {
+      // gallop: pre[lo] <= t throughout, the answer lies in [lo, hi]
+      int64_t lo = last + 1, hi = r1, step = 1;
+      while (lo + step <= r1) {
+        if (pre[lo + step] > t) {
+          hi = lo + step - 1;
+          break;
+        }
+        lo += step;
+        step <<= 1;
+      }
+      e = find_entry(pre, lo, hi, t);
+    }
     if (e != last) {
       // the entry's term is shared by all its in-neighbours
       last = e;
@@ -334,20 +358,28 @@ __global__ __launch_bounds__(kInsertThreads) void insert_kernel(
       const int32_t d = din[en.x];
       term = (en.V + (uint64_t)(d >> 1)) / (uint64_t)d;
       base = reg_off[en.o - o0];
-      mask = (uint32_t)(reg_off[en.o - o0 + 1] - base - 1);
+      const long long size = reg_off[en.o - o0 + 1] - base;
+      mask = (uint32_t)(size - 1);
+      dense = size >= (long long)n;
       row = in_off[en.x];
       first = pre[e];
     }
     const int32_t q = in_idx[row + (t - first)];
-    uint32_t h = slot_hash((uint32_t)q) & mask;
-    while (true) {
-      const int32_t k = keys[base + h];
-      if (k == q) break;
-      if (k == -1) {
-        const int32_t old = atomicCAS(&keys[base + h], -1, q);
-        if (old == -1 || old == q) break;
+    uint32_t h;
+    if (dense) {
+      h = (uint32_t)q;
+      if (keys[base + h] != q) keys[base + h] = q;
+    } else {
+      h = slot_hash((uint32_t)q) & mask;
+      while (true) {
+        const int32_t k = keys[base + h];
+        if (k == q) break;
+        if (k == -1) {
+          const int32_t old = atomicCAS(&keys[base + h], -1, q);
+          if (old == -1 || old == q) break;
+        }
+        h = (h + 1) & mask;
       }
-      h = (h + 1) & mask;
     }
     if (term) atomicAdd(&vals[base + h], term);
   }
@@ -556,7 +588,7 @@ es_status ensure_graph_sums(es_ctx* ctx, const es_graph* g) {
 // Build (P^T)^j(x, .) for every origin x = origins[i] up to depth[i] steps and
 // return each level's sums.  Origins are independent; they are processed in
 // passes of at most kSlotBudget hash slots (a single origin's region never
-// exceeds 4n slots).
+// exceeds max(64, 2n) slots).
 es_status propagate(es_ctx* ctx, const es_graph* g, const std::vector<int32_t>& origins,
                     const std::vector<int32_t>& depth, std::vector<OriginLevel>& res) {
   const int32_t no = (int32_t)origins.size();
@@ -566,6 +598,7 @@ es_status propagate(es_ctx* ctx, const es_graph* g, const std::vector<int32_t>& 
   es_status st;
   int32_t maxd = 0;
   for (int32_t d : depth) maxd = std::max(maxd, d);
+  const int64_t dense_cap = pow2_at_least(std::max<int64_t>(n, 64));
   const size_t nstat = (size_t)no * (kMaxLevel + 1) * kStatWords;
   auto* misc = (unsigned long long*)workspace(ctx, kWsLdeStats, 8 * nstat + 8 * (size_t)no + 64, &st);
   if (!misc) return st;
@@ -597,6 +630,9 @@ es_status propagate(es_ctx* ctx, const es_graph* g, const std::vector<int32_t>& 
       if (depth[i] <= j || ins[i] == 0) continue;
       const int64_t distinct = (int64_t)std::min<uint64_t>(ins[i], (uint64_t)n);
       cap[i] = std::max<int64_t>(64, pow2_at_least(2 * distinct));  // whole 64-slot pages
+      // a hash region no smaller than the dense one is replaced by it
+      // (regions below n slots are hashed, those of n or more dense)
+      cap[i] = std::min(cap[i], dense_cap);
       if (depth[i] > j + 1) next_cap += distinct;
     }
     const int nxt_slot = cur_slot == kWsLdeEnt0 ? kWsLdeEnt1 : kWsLdeEnt0;
@@ -644,7 +680,8 @@ es_status propagate(es_ctx* ctx, const es_graph* g, const std::vector<int32_t>& 
         if (total > 0) {
           const int64_t ib = (total + (int64_t)kInsertThreads * kInsertPer - 1) / ((int64_t)kInsertThreads * kInsertPer);
           insert_kernel<<<(unsigned)ib, kInsertThreads, 0, ctx->stream>>>(total, ne, ent_cur, pre, g->in_off,
-                                                                          g->in_idx, g->din_int, reg, o0, keys, vals);
+                                                                          g->in_idx, g->din_int, reg, o0, n, keys,
+                                                                          vals);
         }
         const int cgrid = (int)std::min<int64_t>(ceil_div(S, tb), (int64_t)ctx->num_cus * 32);
         compact_kernel<<<cgrid, tb, 0, ctx->stream>>>(S, reg, o1 - o0, o0, keys, vals, g->din_int, g->inv_din,
