@@ -370,7 +370,10 @@ es_status es_mlp_infer(es_ctx* ctx, const float* weights, const float* feats, in
  * of which M(k) met.  Loss: sum_k w_k BCE(y_k, p_k) / sum_k w_k with the
  * observed meeting fraction y_k = M/R and weight w_k = min(R, 65536) (rows
  * with R = 0 carry no weight).  grad: device float32 [num_params]; loss
- * (host, nullable) receives the loss (synchronizes). */
+ * (host, nullable) receives the loss (synchronizes).  The sums over rows are
+ * formed per block of 256 rows and added in block order, so the gradient
+ * and a training run are the same bit for bit on every call; the context
+ * keeps about 19 KB of device scratch per 256 rows for them. */
 es_status es_mlp_grad(es_ctx* ctx, const float* weights, const float* feats, const uint64_t* R, const uint64_t* M,
                       int64_t N, double c, float* grad, double* loss);
 /* `epochs` full-batch Adam steps (lr, betas 0.9 / 0.999, eps 1e-8) on that

@@ -28,8 +28,9 @@ constexpr int OFF_W1 = 0, OFF_B1 = H * NF, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 
               OFF_B3 = OFF_W3 + H, NPARAM = OFF_B3 + 1;
 constexpr float V_FLOOR = 1e-6f;
 constexpr int kInferThreads = 256;
-constexpr int kGradThreads = 128;
-constexpr int kPad = H + 1;  // LDS row stride (conflict-free column access)
+constexpr int kGradThreads = 256;  // rows per gradient block
+constexpr int kPartStride = (NPARAM + 3) & ~3;  // floats per block partial gradient
+constexpr int kSumGroup = 64;                  // partials added per first-level sum
 constexpr uint64_t kWeightCap = 65536;  // a node's weight in the loss: min(R(k), cap)
 
 // ---- features ----------------------------------------------------------------
@@ -207,19 +208,30 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(int64_t N, const f
   }
 }
 
-// Unnormalised gradient of sum_i w_i BCE(y_i, p_i) and the loss sum, accumulated
-// atomically into grad[NPARAM] and acc[0] (loss), acc[1] (sum of weights).
+// LDS index of element c of row q in a [rows][H] array whose 16-byte groups
+// are permuted per row (group g of row q sits at g ^ (q mod 16)): 64 lanes
+// writing their own rows at one column spread over 16 bank groups, and row
+// reads (one row for the whole wave) and column reads stay conflict-free.
+__device__ __forceinline__ int swz(int q, int c) { return q * H + ((((c >> 2) ^ (q & 15)) << 2) | (c & 3)); }
+
+// Unnormalised gradient of sum_i w_i BCE(y_i, p_i) over the block's rows and
+// the loss sum: part[b][NPARAM] and pacc[b][2] (loss, sum of weights) for
+// block b, each entry written by one thread (the blocks' partials are added
+// in block order afterwards, so the gradient does not depend on timing).
 // Labels: y = M(k)/R(k), the observed meeting fraction of R(k) pairs, weight
-// min(R(k), cap) (rows with R(k) = 0 carry no weight).
+// min(R(k), cap) (rows with R(k) = 0 carry no weight).  One row per thread:
+// the forward pass and dh1 run in registers against the weights in LDS
+// (16-byte broadcast reads); the block's sums over its rows (dW2 as 4 x 4
+// register tiles per thread, the rest as column sums) read the rows back
+// from LDS.
 __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const float* __restrict__ F,
                                                             const uint64_t* __restrict__ Rn,
                                                             const uint64_t* __restrict__ Mn,
                                                             const float* __restrict__ w, float c,
-                                                            float* __restrict__ grad, double* __restrict__ acc) {
-  __shared__ float sw[NPARAM];
-  __shared__ float H1[kGradThreads * kPad];   // h1, later dh1
-  __shared__ float D2[kGradThreads * kPad];   // dh2 (pre-activation gradient of layer 2)
-  __shared__ float G3[kGradThreads * kPad];   // gz * h2
+                                                            float* __restrict__ part, double* __restrict__ pacc) {
+  __shared__ __align__(16) float sw[NPARAM];
+  __shared__ __align__(16) float HS[kGradThreads * H];  // h1 rows, later dh1 rows
+  __shared__ __align__(16) float DS[kGradThreads * H];  // h2 rows, later dz2 rows
   __shared__ float XS[kGradThreads * NF];
   __shared__ float GZ[kGradThreads];
   __shared__ double red[2][kGradThreads / 64];
@@ -227,6 +239,7 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
   const int t = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kGradThreads + t;
   const bool live = i < N;
+  float* __restrict__ grad = part + (int64_t)blockIdx.x * kPartStride;
   float x[NF];
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
@@ -234,23 +247,46 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
     XS[t * NF + j] = x[j];
   }
   __syncthreads();
-  // each thread works on its own LDS rows (stride kPad: conflict-free)
-  float* h1 = H1 + t * kPad;
-  float* d2 = D2 + t * kPad;
-  float* g3 = G3 + t * kPad;
+  // layer 1: h1 in registers, its ReLU pattern in m1
+  float h[H];
+  uint64_t m1 = 0;
+#pragma unroll
   for (int a = 0; a < H; ++a) {
     float s = sw[OFF_B1 + a];
 #pragma unroll
-    for (int j = 0; j < NF; ++j) s += sw[OFF_W1 + a * NF + j] * x[j];
-    h1[a] = s > 0.0f ? s : 0.0f;
+    for (int j = 0; j < NF; ++j) s = fmaf(sw[OFF_W1 + a * NF + j], x[j], s);
+    h[a] = s > 0.0f ? s : 0.0f;
+    m1 |= (uint64_t)(s > 0.0f ? 1u : 0u) << a;
   }
+#pragma unroll
+  for (int g = 0; g < H / 4; ++g)
+    *(float4*)&HS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(h[4 * g], h[4 * g + 1], h[4 * g + 2], h[4 * g + 3]);
+  // layer 2: h2 rows to LDS, their ReLU pattern in m2
   float z = sw[OFF_B3];
-  for (int a = 0; a < H; ++a) {
-    float s = sw[OFF_B2 + a];
-#pragma unroll 8
-    for (int j = 0; j < H; ++j) s += sw[OFF_W2 + a * H + j] * h1[j];
-    d2[a] = s;  // pre-activation, turned into its gradient below
-    z += sw[OFF_W3 + a] * (s > 0.0f ? s : 0.0f);
+  uint64_t m2 = 0;
+  for (int a = 0; a < H; a += 4) {
+    // four rows of W2 at once: independent sums
+    float s[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = sw[OFF_B2 + a + k];
+#pragma unroll
+    for (int g = 0; g < H / 4; ++g) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 v = *(const float4*)&sw[OFF_W2 + (a + k) * H + 4 * g];
+        s[k] = fmaf(v.x, h[4 * g], s[k]);
+        s[k] = fmaf(v.y, h[4 * g + 1], s[k]);
+        s[k] = fmaf(v.z, h[4 * g + 2], s[k]);
+        s[k] = fmaf(v.w, h[4 * g + 3], s[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float r = s[k] > 0.0f ? s[k] : 0.0f;
+      DS[swz(t, a + k)] = r;
+      m2 |= (uint64_t)(s[k] > 0.0f ? 1u : 0u) << (a + k);
+      z = fmaf(sw[OFF_W3 + a + k], r, z);
+    }
   }
   const float sig = 1.0f / (1.0f + expf(-z));
   const float p = c * sig;
@@ -266,11 +302,6 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
     wsum = ww;
   }
   GZ[t] = gz;
-  for (int a = 0; a < H; ++a) {
-    const float a2 = d2[a];
-    g3[a] = a2 > 0.0f ? gz * a2 : 0.0f;
-    d2[a] = a2 > 0.0f ? gz * sw[OFF_W3 + a] : 0.0f;
-  }
   for (int m = 32; m > 0; m >>= 1) {
     lsum += __shfl_xor(lsum, m, 64);
     wsum += __shfl_xor(wsum, m, 64);
@@ -286,59 +317,115 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
       l += red[0][q];
       ws += red[1][q];
     }
-    atomicAdd(&acc[0], l);
-    atomicAdd(&acc[1], ws);
+    pacc[2 * (int64_t)blockIdx.x] = l;
+    pacc[2 * (int64_t)blockIdx.x + 1] = ws;
   }
-  // dW2[a][j] = sum_t D2[t][a] H1[t][j]; thread t owns entries e = t, t + 128, ...
-  for (int e = t; e < H * H; e += kGradThreads) {
-    const int a = e / H, j = e - a * H;
-    float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s += D2[q * kPad + a] * H1[q * kPad + j];
-    atomicAdd(&grad[OFF_W2 + e], s);
-  }
+  // dW3[a] = sum_q gz_q h2_{q,a}, db3 = sum_q gz_q
   if (t < H) {
-    float sb2 = 0.0f, sw3 = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) {
-      sb2 += D2[q * kPad + t];
-      sw3 += G3[q * kPad + t];
-    }
-    atomicAdd(&grad[OFF_B2 + t], sb2);
-    atomicAdd(&grad[OFF_W3 + t], sw3);
+    float s = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) s = fmaf(GZ[q], DS[swz(q, t)], s);
+    grad[OFF_W3 + t] = s;
   } else if (t == H) {
     float s = 0.0f;
     for (int q = 0; q < kGradThreads; ++q) s += GZ[q];
-    atomicAdd(&grad[OFF_B3], s);
+    grad[OFF_B3] = s;
   }
   __syncthreads();
-  // dh1[j] = [h1_j > 0] sum_a W2[a][j] D2[t][a], written over G3
-  for (int j = 0; j < H; ++j) {
-    float s = 0.0f;
-#pragma unroll 8
-    for (int a = 0; a < H; ++a) s += sw[OFF_W2 + a * H + j] * d2[a];
-    g3[j] = h1[j] > 0.0f ? s : 0.0f;
+  // dz2 rows (pre-activation gradient of layer 2) over the h2 rows
+#pragma unroll
+  for (int g = 0; g < H / 4; ++g) {
+    float d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = 4 * g + k;
+      d[k] = ((m2 >> a) & 1ull) ? gz * sw[OFF_W3 + a] : 0.0f;
+    }
+    *(float4*)&DS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(d[0], d[1], d[2], d[3]);
   }
   __syncthreads();
-  for (int e = t; e < H * NF; e += kGradThreads) {
-    const int a = e / NF, j = e - a * NF;
-    float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s += G3[q * kPad + a] * XS[q * NF + j];
-    atomicAdd(&grad[OFF_W1 + e], s);
+  // dW2[a][j] = sum_q dz2_{q,a} h1_{q,j}: thread t sums the 4 x 4 tile at
+  // a = 4 (t / 16), j = 4 (t mod 16)
+  {
+    const int ga = t >> 4, gj = t & 15;
+    float s[4][4] = {};
+    for (int q = 0; q < kGradThreads; ++q) {
+      const float4 dv = *(const float4*)&DS[q * H + ((ga ^ (q & 15)) << 2)];
+      const float4 hv = *(const float4*)&HS[q * H + ((gj ^ (q & 15)) << 2)];
+      const float dd[4] = {dv.x, dv.y, dv.z, dv.w}, hh[4] = {hv.x, hv.y, hv.z, hv.w};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[r][k] = fmaf(dd[r], hh[k], s[r][k]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) grad[OFF_W2 + (4 * ga + r) * H + 4 * gj + k] = s[r][k];
   }
+  // db2[a] = sum_q dz2_{q,a}
   if (t < H) {
     float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s += G3[q * kPad + t];
-    atomicAdd(&grad[OFF_B1 + t], s);
+    for (int q = 0; q < kGradThreads; ++q) s += DS[swz(q, t)];
+    grad[OFF_B2 + t] = s;
   }
+  __syncthreads();
+  // dh1[j] = [h1_j > 0] sum_a W2[a][j] dz2_a, written over the h1 rows
+  float dh[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) dh[j] = 0.0f;
+  for (int a = 0; a < H; ++a) {
+    const float d = ((m2 >> a) & 1ull) ? gz * sw[OFF_W3 + a] : 0.0f;
+    const float4* wr = (const float4*)&sw[OFF_W2 + a * H];
+#pragma unroll
+    for (int g = 0; g < H / 4; ++g) {
+      const float4 v = wr[g];
+      dh[4 * g] = fmaf(d, v.x, dh[4 * g]);
+      dh[4 * g + 1] = fmaf(d, v.y, dh[4 * g + 1]);
+      dh[4 * g + 2] = fmaf(d, v.z, dh[4 * g + 2]);
+      dh[4 * g + 3] = fmaf(d, v.w, dh[4 * g + 3]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < H / 4; ++g) {
+    float e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = ((m1 >> (4 * g + k)) & 1ull) ? dh[4 * g + k] : 0.0f;
+    *(float4*)&HS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(e[0], e[1], e[2], e[3]);
+  }
+  __syncthreads();
+  // dW1[a][j] = sum_q dh1_{q,a} x_{q,j}, db1[a] = sum_q dh1_{q,a}
+  if (t < H) {
+    float s[NF] = {};
+    float sb = 0.0f;
+    for (int q = 0; q < kGradThreads; ++q) {
+      const float v = HS[swz(q, t)];
+      sb += v;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) s[j] = fmaf(v, XS[q * NF + j], s[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) grad[OFF_W1 + t * NF + j] = s[j];
+    grad[OFF_B1 + t] = sb;
+  }
+}
+
+// out[g][j] = sum of in[r][j] over rows r in [g G, min((g + 1) G, nrows)),
+// added in row order (rows of `stride` elements, ncols used).
+template <typename T>
+__global__ void sum_rows_kernel(int64_t nrows, int32_t G, int32_t ncols, int32_t stride, const T* __restrict__ in,
+                                T* __restrict__ out) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * G;
+  const int64_t r1 = min(nrows, r0 + G);
+  T s = 0;
+  for (int64_t r = r0; r < r1; ++r) s += in[r * stride + j];
+  out[(int64_t)blockIdx.y * stride + j] = s;
 }
 
 __global__ void zero_f32(int n, float* p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
-}
-
-__global__ void zero_f64(int n, double* p) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
 }
 
 // grad /= sum of weights
@@ -365,6 +452,52 @@ __global__ void record_loss(const double* __restrict__ acc, float* __restrict__ 
 }
 
 bool valid_c(double c) { return c > 0.0 && c <= 0.99; }
+
+// Scratch of one gradient evaluation over N rows: the blocks' partials and the
+// first-level sums, after `lead` floats the caller keeps for itself (Adam's
+// state in training).
+struct GradScratch {
+  float* lead;    // lead floats
+  float* part;    // [nb][kPartStride], then [ng][kPartStride]
+  double* acc;    // acc[0] loss, acc[1] sum of weights
+  double* pacc;   // [nb][2], then [ng][2]
+  int64_t nb, ng;
+  int32_t G;      // blocks per first-level sum
+};
+
+es_status grad_scratch(es_ctx* ctx, int64_t N, size_t lead, GradScratch* gs) {
+  es_status st;
+  gs->nb = (N + kGradThreads - 1) / kGradThreads;
+  gs->G = (int32_t)std::max<int64_t>(kSumGroup, (gs->nb + 32767) / 32768);  // at most 32768 first-level sums
+  gs->ng = (gs->nb + gs->G - 1) / gs->G;
+  const size_t lead4 = (lead + 3) & ~(size_t)3;
+  auto* f = (float*)workspace(ctx, kWsMlpGrad, sizeof(float) * (lead4 + (size_t)(gs->nb + gs->ng) * kPartStride), &st);
+  if (!f) return st;
+  auto* d = (double*)workspace(ctx, kWsMlpAcc, sizeof(double) * (2 + 2 * (size_t)(gs->nb + gs->ng)), &st);
+  if (!d) return st;
+  gs->lead = f;
+  gs->part = f + lead4;
+  gs->acc = d;
+  gs->pacc = d + 2;
+  return ES_OK;
+}
+
+// grad_out[NPARAM] and gs.acc[0..1]: the block partials of the rows added in
+// block order (two levels), so the result is the same on every run.
+void launch_grad(es_ctx* ctx, const GradScratch& gs, int64_t N, const float* feats, const uint64_t* R,
+                 const uint64_t* M, const float* weights, double c, float* grad_out) {
+  float* part2 = gs.part + gs.nb * kPartStride;
+  double* pacc2 = gs.pacc + 2 * gs.nb;
+  grad_kernel<<<(unsigned)gs.nb, kGradThreads, 0, ctx->stream>>>(N, feats, R, M, weights, (float)c, gs.part,
+                                                                  gs.pacc);
+  const unsigned cols = (unsigned)ceil_div(NPARAM, 256);
+  sum_rows_kernel<float><<<dim3(cols, (unsigned)gs.ng), 256, 0, ctx->stream>>>(gs.nb, gs.G, NPARAM, kPartStride,
+                                                                              gs.part, part2);
+  sum_rows_kernel<float><<<dim3(cols, 1), 256, 0, ctx->stream>>>(gs.ng, (int32_t)gs.ng, NPARAM, kPartStride, part2,
+                                                                grad_out);
+  sum_rows_kernel<double><<<dim3(1, (unsigned)gs.ng), 64, 0, ctx->stream>>>(gs.nb, gs.G, 2, 2, gs.pacc, pacc2);
+  sum_rows_kernel<double><<<dim3(1, 1), 64, 0, ctx->stream>>>(gs.ng, (int32_t)gs.ng, 2, 2, pacc2, gs.acc);
+}
 
 }  // namespace
 
@@ -451,13 +584,10 @@ es_status es_mlp_grad(es_ctx* ctx, const float* weights, const float* feats, con
   if (!ctx || !weights || !feats || !R || !M || N < 1 || !grad) return ES_EINVAL;
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
-  es_status st;
-  auto* acc = (double*)workspace(ctx, kWsMlpAcc, 64, &st);
-  if (!acc) return st;
-  zero_f32<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(NPARAM, grad);
-  zero_f64<<<1, 64, 0, ctx->stream>>>(2, acc);
-  grad_kernel<<<(unsigned)((N + kGradThreads - 1) / kGradThreads), kGradThreads, 0, ctx->stream>>>(
-      N, feats, R, M, weights, (float)c, grad, acc);
+  GradScratch gs;
+  ES_TRY(grad_scratch(ctx, N, 0, &gs));
+  double* acc = gs.acc;
+  launch_grad(ctx, gs, N, feats, R, M, weights, c, grad);
   normalise_kernel<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(grad, acc);
   ES_CHECK_HIP(ctx, hipGetLastError());
   if (loss) {
@@ -475,23 +605,20 @@ es_status es_mlp_train(es_ctx* ctx, const float* feats, const uint64_t* R, const
   if (!valid_c(c)) return fail(ctx, ES_EINVAL, "c=%g outside (0, 0.99]", c);
   ES_CHECK_HIP(ctx, hipSetDevice(ctx->device));
   es_status st;
-  auto* grad = (float*)workspace(ctx, kWsMlpGrad, sizeof(float) * 3 * NPARAM, &st);
-  if (!grad) return st;
+  GradScratch gs;
+  ES_TRY(grad_scratch(ctx, N, 3 * (size_t)NPARAM, &gs));
+  float* grad = gs.lead;
   float* m = grad + NPARAM;
   float* v = grad + 2 * NPARAM;
-  auto* acc = (double*)workspace(ctx, kWsMlpAcc, 64, &st);
-  if (!acc) return st;
+  double* acc = gs.acc;
   auto* dl = (float*)workspace(ctx, kWsMlpLoss, sizeof(float) * (size_t)epochs, &st);
   if (!dl) return st;
   zero_f32<<<ceil_div(3 * NPARAM, 256), 256, 0, ctx->stream>>>(3 * NPARAM, grad);
-  const unsigned gblocks = (unsigned)((N + kGradThreads - 1) / kGradThreads);
   double b1t = 1.0, b2t = 1.0;
   for (int32_t ep = 0; ep < epochs; ++ep) {
     b1t *= 0.9;
     b2t *= 0.999;
-    zero_f32<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(NPARAM, grad);
-    zero_f64<<<1, 64, 0, ctx->stream>>>(2, acc);
-    grad_kernel<<<gblocks, kGradThreads, 0, ctx->stream>>>(N, feats, R, M, weights, (float)c, grad, acc);
+    launch_grad(ctx, gs, N, feats, R, M, weights, c, grad);
     record_loss<<<1, 1, 0, ctx->stream>>>(acc, dl + ep);
     adam_kernel<<<ceil_div(NPARAM, 256), 256, 0, ctx->stream>>>(weights, grad, m, v, acc, lr, (float)(1.0 - b1t),
                                                                  (float)(1.0 - b2t));

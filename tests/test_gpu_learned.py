@@ -85,7 +85,7 @@ def test_inference_matches_oracle(es, ctx):
 
 def test_gradient_matches_oracle(es, ctx):
     rng = np.random.default_rng(5)
-    N = 3000  # several 128-row tiles and a ragged tail
+    N = 3000  # several 256-row blocks and a ragged tail
     X = rng.normal(0, 1.0, (N, 6)).astype(np.float32)
     R = rng.integers(0, 100000, N).astype(np.uint64)
     R[:50] = 0
@@ -105,6 +105,30 @@ def test_gradient_matches_oracle(es, ctx):
     bad = np.flatnonzero(np.abs(g - ref_g) > tol)
     assert bad.size == 0, (bad[:10], g[bad[:10]], ref_g[bad[:10]])
     assert np.linalg.norm(g - ref_g) <= 1e-4 * np.linalg.norm(ref_g)
+
+
+def test_gradient_and_training_are_reproducible(es, ctx):
+    """The blocks' partial gradients are added in block order: the gradient
+    and a whole training run give the same bits every time (also with more
+    blocks than one first-level sum takes)."""
+    rng = np.random.default_rng(8)
+    N = 70_001  # 274 blocks of 256 rows: five first-level sums, the last partial
+    X = torch.as_tensor(rng.normal(0, 1.0, (N, 6)).astype(np.float32)).cuda()
+    R = torch.as_tensor(rng.integers(0, 5000, N).astype(np.uint64)).cuda()
+    M = torch.as_tensor((R.cpu().numpy() * rng.uniform(0, C, N)).astype(np.uint64)).cuda()
+    theta = weights_tensor(mlp.init_params(4))
+    grads = []
+    for _ in range(2):
+        g = torch.empty(mlp.NPARAM, dtype=torch.float32, device="cuda")
+        es.es_mlp_grad(ctx, theta, X, R, M, N, C, g)
+        grads.append(g)
+    assert torch.equal(grads[0].view(torch.int32), grads[1].view(torch.int32))
+    from paper_2004_03493_amd import learned
+    w1, l1 = learned.train(ctx, X, R, M, C, epochs=30)
+    w2, l2 = learned.train(ctx, X, R, M, C, epochs=30)
+    assert torch.equal(w1.view(torch.int32), w2.view(torch.int32))
+    assert np.array_equal(np.asarray(l1), np.asarray(l2))
+    assert l1[-1] < l1[0]
 
 
 def test_weighted_budget_bitwise(es, ctx, rmat32k):
