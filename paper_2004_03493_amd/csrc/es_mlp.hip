@@ -28,7 +28,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = H * NF, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 
               OFF_B3 = OFF_W3 + H, NPARAM = OFF_B3 + 1;
 constexpr float V_FLOOR = 1e-6f;
 constexpr int kInferThreads = 256;
-constexpr int kGradThreads = 256;  // rows per gradient block
+constexpr int kGradRows = 256;                 // rows per gradient block
+constexpr int kGradThreads = 2 * kGradRows;    // two threads per row
 constexpr int kPartStride = (NPARAM + 3) & ~3;  // floats per block partial gradient
 constexpr int kSumGroup = 64;                  // partials added per first-level sum
 constexpr uint64_t kWeightCap = 65536;  // a node's weight in the loss: min(R(k), cap)
@@ -219,35 +220,38 @@ __device__ __forceinline__ int swz(int q, int c) { return q * H + ((((c >> 2) ^ 
 // block b, each entry written by one thread (the blocks' partials are added
 // in block order afterwards, so the gradient does not depend on timing).
 // Labels: y = M(k)/R(k), the observed meeting fraction of R(k) pairs, weight
-// min(R(k), cap) (rows with R(k) = 0 carry no weight).  One row per thread:
-// the forward pass and dh1 run in registers against the weights in LDS
-// (16-byte broadcast reads); the block's sums over its rows (dW2 as 4 x 4
-// register tiles per thread, the rest as column sums) read the rows back
-// from LDS.
+// min(R(k), cap) (rows with R(k) = 0 carry no weight).  Two threads per row,
+// each for half of the hidden units (the halves are whole waves): the
+// forward pass and dh1 run in registers against the weights in LDS (16-byte
+// broadcast reads); the block's sums over its rows (dW2 as 2 x 4 register
+// tiles per thread, the rest as column sums) read the rows back from LDS.
 __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const float* __restrict__ F,
                                                             const uint64_t* __restrict__ Rn,
                                                             const uint64_t* __restrict__ Mn,
                                                             const float* __restrict__ w, float c,
                                                             float* __restrict__ part, double* __restrict__ pacc) {
   __shared__ __align__(16) float sw[NPARAM];
-  __shared__ __align__(16) float HS[kGradThreads * H];  // h1 rows, later dh1 rows
-  __shared__ __align__(16) float DS[kGradThreads * H];  // h2 rows, later dz2 rows
-  __shared__ float XS[kGradThreads * NF];
-  __shared__ float GZ[kGradThreads];
-  __shared__ double red[2][kGradThreads / 64];
+  __shared__ __align__(16) float HS[kGradRows * H];  // h1 rows, later dh1 rows
+  __shared__ __align__(16) float DS[kGradRows * H];  // h2 rows, later dz2 rows
+  __shared__ float XS[kGradRows * NF];
+  __shared__ float GZ[kGradRows];
+  __shared__ float ZP[2][kGradRows];  // each half's share of z
+  __shared__ double red[2][kGradRows / 64];
   load_weights(w, sw);
   const int t = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kGradThreads + t;
+  const int q0 = t & (kGradRows - 1);  // this thread's row
+  const int hf = t / kGradRows;        // its half of the hidden units
+  const int64_t i = (int64_t)blockIdx.x * kGradRows + q0;
   const bool live = i < N;
   float* __restrict__ grad = part + (int64_t)blockIdx.x * kPartStride;
   float x[NF];
 #pragma unroll
-  for (int j = 0; j < NF; ++j) {
-    x[j] = live ? F[i * NF + j] : 0.0f;
-    XS[t * NF + j] = x[j];
-  }
+  for (int j = 0; j < NF; ++j) x[j] = live ? F[i * NF + j] : 0.0f;
+  if (hf == 0)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) XS[q0 * NF + j] = x[j];
   __syncthreads();
-  // layer 1: h1 in registers, its ReLU pattern in m1
+  // layer 1, all units in both halves: h1 in registers, its ReLU pattern in m1
   float h[H];
   uint64_t m1 = 0;
 #pragma unroll
@@ -258,14 +262,21 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
     h[a] = s > 0.0f ? s : 0.0f;
     m1 |= (uint64_t)(s > 0.0f ? 1u : 0u) << a;
   }
+  // this half's 16-byte groups of the h1 row
+  if (hf == 0) {
 #pragma unroll
-  for (int g = 0; g < H / 4; ++g)
-    *(float4*)&HS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(h[4 * g], h[4 * g + 1], h[4 * g + 2], h[4 * g + 3]);
-  // layer 2: h2 rows to LDS, their ReLU pattern in m2
-  float z = sw[OFF_B3];
+    for (int g = 0; g < H / 8; ++g)
+      *(float4*)&HS[q0 * H + ((g ^ (q0 & 15)) << 2)] = make_float4(h[4 * g], h[4 * g + 1], h[4 * g + 2], h[4 * g + 3]);
+  } else {
+#pragma unroll
+    for (int g = H / 8; g < H / 4; ++g)
+      *(float4*)&HS[q0 * H + ((g ^ (q0 & 15)) << 2)] = make_float4(h[4 * g], h[4 * g + 1], h[4 * g + 2], h[4 * g + 3]);
+  }
+  // layer 2 for this half's units, four rows of W2 at a time: h2 to LDS,
+  // the ReLU pattern in m2 (this half's bits), the share of z in ZP
   uint64_t m2 = 0;
-  for (int a = 0; a < H; a += 4) {
-    // four rows of W2 at once: independent sums
+  float zp = 0.0f;
+  for (int a = hf * (H / 2); a < (hf + 1) * (H / 2); a += 4) {
     float s[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) s[k] = sw[OFF_B2 + a + k];
@@ -283,11 +294,14 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float r = s[k] > 0.0f ? s[k] : 0.0f;
-      DS[swz(t, a + k)] = r;
+      DS[swz(q0, a + k)] = r;
       m2 |= (uint64_t)(s[k] > 0.0f ? 1u : 0u) << (a + k);
-      z = fmaf(sw[OFF_W3 + a + k], r, z);
+      zp = fmaf(sw[OFF_W3 + a + k], r, zp);
     }
   }
+  ZP[hf][q0] = zp;
+  __syncthreads();
+  const float z = (sw[OFF_B3] + ZP[0][q0]) + ZP[1][q0];
   const float sig = 1.0f / (1.0f + expf(-z));
   const float p = c * sig;
   float gz = 0.0f;
@@ -298,22 +312,26 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
     const float ww = (float)(rr < kWeightCap ? rr : kWeightCap);
     // d/dz of w * BCE(y, c sigmoid(z)) = w (1 - p/c) (-y + (1 - y) p/(1 - p))
     gz = ww * (1.0f - p / c) * (-yy + (1.0f - yy) * p / (1.0f - p));
-    lsum = -(double)ww * ((double)yy * log((double)p) + (1.0 - (double)yy) * log1p(-(double)p));
-    wsum = ww;
+    if (hf == 0) {
+      lsum = -(double)ww * ((double)yy * log((double)p) + (1.0 - (double)yy) * log1p(-(double)p));
+      wsum = ww;
+    }
   }
-  GZ[t] = gz;
-  for (int m = 32; m > 0; m >>= 1) {
-    lsum += __shfl_xor(lsum, m, 64);
-    wsum += __shfl_xor(wsum, m, 64);
-  }
-  if ((t & 63) == 0) {
-    red[0][t >> 6] = lsum;
-    red[1][t >> 6] = wsum;
+  if (hf == 0) {
+    GZ[q0] = gz;
+    for (int m = 32; m > 0; m >>= 1) {
+      lsum += __shfl_xor(lsum, m, 64);
+      wsum += __shfl_xor(wsum, m, 64);
+    }
+    if ((t & 63) == 0) {
+      red[0][t >> 6] = lsum;
+      red[1][t >> 6] = wsum;
+    }
   }
   __syncthreads();
   if (t == 0) {
     double l = 0.0, ws = 0.0;
-    for (int q = 0; q < kGradThreads / 64; ++q) {
+    for (int q = 0; q < kGradRows / 64; ++q) {
       l += red[0][q];
       ws += red[1][q];
     }
@@ -323,89 +341,91 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
   // dW3[a] = sum_q gz_q h2_{q,a}, db3 = sum_q gz_q
   if (t < H) {
     float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s = fmaf(GZ[q], DS[swz(q, t)], s);
+    for (int q = 0; q < kGradRows; ++q) s = fmaf(GZ[q], DS[swz(q, t)], s);
     grad[OFF_W3 + t] = s;
   } else if (t == H) {
     float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s += GZ[q];
+    for (int q = 0; q < kGradRows; ++q) s += GZ[q];
     grad[OFF_B3] = s;
   }
   __syncthreads();
-  // dz2 rows (pre-activation gradient of layer 2) over the h2 rows
+  // dz2 (pre-activation gradient of layer 2), this half's groups, over the h2 rows
 #pragma unroll
-  for (int g = 0; g < H / 4; ++g) {
+  for (int g = 0; g < H / 8; ++g) {
+    const int gg = hf * (H / 8) + g;
     float d[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int a = 4 * g + k;
+      const int a = 4 * gg + k;
       d[k] = ((m2 >> a) & 1ull) ? gz * sw[OFF_W3 + a] : 0.0f;
     }
-    *(float4*)&DS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(d[0], d[1], d[2], d[3]);
+    *(float4*)&DS[q0 * H + ((gg ^ (q0 & 15)) << 2)] = make_float4(d[0], d[1], d[2], d[3]);
   }
   __syncthreads();
-  // dW2[a][j] = sum_q dz2_{q,a} h1_{q,j}: thread t sums the 4 x 4 tile at
-  // a = 4 (t / 16), j = 4 (t mod 16)
+  // dW2[a][j] = sum_q dz2_{q,a} h1_{q,j}: thread t sums the 2 x 4 tile at
+  // a = 2 (t / 16), j = 4 (t mod 16)
   {
-    const int ga = t >> 4, gj = t & 15;
-    float s[4][4] = {};
-    for (int q = 0; q < kGradThreads; ++q) {
-      const float4 dv = *(const float4*)&DS[q * H + ((ga ^ (q & 15)) << 2)];
+    const int a0 = 2 * (t >> 4), gj = t & 15;
+    float s[2][4] = {};
+    for (int q = 0; q < kGradRows; ++q) {
+      const float2 dv = *(const float2*)&DS[q * H + ((((a0 >> 2) ^ (q & 15)) << 2) | (a0 & 3))];
       const float4 hv = *(const float4*)&HS[q * H + ((gj ^ (q & 15)) << 2)];
-      const float dd[4] = {dv.x, dv.y, dv.z, dv.w}, hh[4] = {hv.x, hv.y, hv.z, hv.w};
+      const float dd[2] = {dv.x, dv.y}, hh[4] = {hv.x, hv.y, hv.z, hv.w};
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[r][k] = fmaf(dd[r], hh[k], s[r][k]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) grad[OFF_W2 + (4 * ga + r) * H + 4 * gj + k] = s[r][k];
+      for (int k = 0; k < 4; ++k) grad[OFF_W2 + (a0 + r) * H + 4 * gj + k] = s[r][k];
   }
   // db2[a] = sum_q dz2_{q,a}
   if (t < H) {
     float s = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) s += DS[swz(q, t)];
+    for (int q = 0; q < kGradRows; ++q) s += DS[swz(q, t)];
     grad[OFF_B2 + t] = s;
   }
   __syncthreads();
-  // dh1[j] = [h1_j > 0] sum_a W2[a][j] dz2_a, written over the h1 rows
-  float dh[H];
+  // dh1[j] = [h1_j > 0] sum_a W2[a][j] dz2_a for this half's j, over the h1 rows
+  {
+    float dh[H / 2];
 #pragma unroll
-  for (int j = 0; j < H; ++j) dh[j] = 0.0f;
-  for (int a = 0; a < H; ++a) {
-    const float d = ((m2 >> a) & 1ull) ? gz * sw[OFF_W3 + a] : 0.0f;
-    const float4* wr = (const float4*)&sw[OFF_W2 + a * H];
+    for (int j = 0; j < H / 2; ++j) dh[j] = 0.0f;
+    for (int a = 0; a < H; ++a) {
+      const float d = DS[swz(q0, a)];
+      const float4* wr = (const float4*)&sw[OFF_W2 + a * H + hf * (H / 2)];
 #pragma unroll
-    for (int g = 0; g < H / 4; ++g) {
-      const float4 v = wr[g];
-      dh[4 * g] = fmaf(d, v.x, dh[4 * g]);
-      dh[4 * g + 1] = fmaf(d, v.y, dh[4 * g + 1]);
-      dh[4 * g + 2] = fmaf(d, v.z, dh[4 * g + 2]);
-      dh[4 * g + 3] = fmaf(d, v.w, dh[4 * g + 3]);
+      for (int g = 0; g < H / 8; ++g) {
+        const float4 v = wr[g];
+        dh[4 * g] = fmaf(d, v.x, dh[4 * g]);
+        dh[4 * g + 1] = fmaf(d, v.y, dh[4 * g + 1]);
+        dh[4 * g + 2] = fmaf(d, v.z, dh[4 * g + 2]);
+        dh[4 * g + 3] = fmaf(d, v.w, dh[4 * g + 3]);
+      }
     }
-  }
 #pragma unroll
-  for (int g = 0; g < H / 4; ++g) {
-    float e[4];
+    for (int g = 0; g < H / 8; ++g) {
+      const int gg = hf * (H / 8) + g;
+      float e[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = ((m1 >> (4 * g + k)) & 1ull) ? dh[4 * g + k] : 0.0f;
-    *(float4*)&HS[t * H + ((g ^ (t & 15)) << 2)] = make_float4(e[0], e[1], e[2], e[3]);
+      for (int k = 0; k < 4; ++k) e[k] = ((m1 >> (4 * gg + k)) & 1ull) ? dh[4 * g + k] : 0.0f;
+      *(float4*)&HS[q0 * H + ((gg ^ (q0 & 15)) << 2)] = make_float4(e[0], e[1], e[2], e[3]);
+    }
   }
   __syncthreads();
-  // dW1[a][j] = sum_q dh1_{q,a} x_{q,j}, db1[a] = sum_q dh1_{q,a}
-  if (t < H) {
-    float s[NF] = {};
-    float sb = 0.0f;
-    for (int q = 0; q < kGradThreads; ++q) {
-      const float v = HS[swz(q, t)];
-      sb += v;
-#pragma unroll
-      for (int j = 0; j < NF; ++j) s[j] = fmaf(v, XS[q * NF + j], s[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < NF; ++j) grad[OFF_W1 + t * NF + j] = s[j];
-    grad[OFF_B1 + t] = sb;
+  // dW1[a][j] = sum_q dh1_{q,a} x_{q,j} (thread a NF + j), db1[a] = sum_q dh1_{q,a}
+  if (t < H * NF) {
+    const int a = t / NF, j = t - a * NF;
+    float s = 0.0f;
+    for (int q = 0; q < kGradRows; ++q) s = fmaf(HS[swz(q, a)], XS[q * NF + j], s);
+    grad[OFF_W1 + t] = s;
+  } else if (t < H * NF + H) {
+    const int a = t - H * NF;
+    float s = 0.0f;
+    for (int q = 0; q < kGradRows; ++q) s += HS[swz(q, a)];
+    grad[OFF_B1 + a] = s;
   }
 }
 
@@ -467,7 +487,7 @@ struct GradScratch {
 
 es_status grad_scratch(es_ctx* ctx, int64_t N, size_t lead, GradScratch* gs) {
   es_status st;
-  gs->nb = (N + kGradThreads - 1) / kGradThreads;
+  gs->nb = (N + kGradRows - 1) / kGradRows;
   gs->G = (int32_t)std::max<int64_t>(kSumGroup, (gs->nb + 32767) / 32768);  // at most 32768 first-level sums
   gs->ng = (gs->nb + gs->G - 1) / gs->G;
   const size_t lead4 = (lead + 3) & ~(size_t)3;
