@@ -247,9 +247,10 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(int64_t N, const flo
   float x[NF];
 #pragma unroll
   for (int j = 0; j < NF; ++j) x[j] = live ? F[i * NF + j] : 0.0f;
-  if (hf == 0)
+  if (hf == 0) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) XS[q0 * NF + j] = x[j];
+  }
   __syncthreads();
   // layer 1, all units in both halves: h1 in registers, its ReLU pattern in m1
   float h[H];
